@@ -1,0 +1,272 @@
+"""Pins of the CPU oracle against facts that do not come from the oracle itself.
+
+Each test fixes one part of the oracle by something independent: exact
+integer constructions, hand-worked closed forms, a high-precision library
+factorisation (mpmath), LAPACK (numpy/scipy), scikit-learn's RBF kernel, and
+rigorous bounds.  A dropped term, a sign error, a transposed operand or a
+wrong index in any oracle routine fails at least one of them.
+"""
+import json
+import os
+
+import mpmath
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+import gp_inputs
+import oracle
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+U = np.finfo(np.float64).eps / 2
+
+
+def _cases():
+    with open(os.path.join(GOLDEN, "closed_form_cases.json")) as f:
+        return json.load(f)
+
+
+# --------------------------------------------------------------- Cholesky ---
+
+@pytest.mark.parametrize("case", _cases()["cases"], ids=lambda c: c["name"])
+def test_closed_form_factor_and_solve(case):
+    A = np.array(case["A"], dtype=np.float64)
+    L, info = oracle.cholesky(A)
+    assert info == 0
+    np.testing.assert_array_equal(L, np.array(case["L"], dtype=np.float64))
+    y = oracle.forward(L, np.array(case["b"], dtype=np.float64))
+    np.testing.assert_allclose(y, case["y"], rtol=0, atol=0)
+    x = oracle.backward(L, y)
+    np.testing.assert_allclose(x, case["x"], rtol=2 * U, atol=0)
+    np.testing.assert_allclose(oracle.solve(L, np.array(case["b"], float)), case["x"], rtol=2 * U)
+
+
+@pytest.mark.parametrize("case", _cases()["not_spd"], ids=lambda c: c["name"])
+def test_not_spd_info(case):
+    _, info = oracle.cholesky(np.array(case["A"], dtype=np.float64))
+    assert info == case["info"]
+
+
+def test_nan_and_negative_pivot_info():
+    A = np.eye(7)
+    A[4, 4] = -1.0
+    assert oracle.cholesky(A)[1] == 5
+    A = np.eye(7)
+    A[2, 2] = np.nan
+    assert oracle.cholesky(A)[1] == 3
+
+
+def test_one_by_one():
+    L, info = oracle.cholesky(np.array([[2.0]]))
+    assert info == 0 and L[0, 0] == np.sqrt(2.0)
+
+
+def test_identity_and_block_diagonal():
+    L, info = oracle.cholesky(np.eye(9))
+    assert info == 0
+    np.testing.assert_array_equal(L, np.eye(9))
+    _, A1 = gp_inputs.known_l0(5, "sparse-dd", seed=1)
+    X, _ = gp_inputs.gp_problem(6, seed=2)
+    A2 = oracle.gp_assemble(X, 1.0, 1.0, 0.1)
+    A = sla.block_diag(A1, A2)
+    L, info = oracle.cholesky(A)
+    L1, _ = oracle.cholesky(A1)
+    L2, _ = oracle.cholesky(A2)
+    assert info == 0
+    np.testing.assert_array_equal(L, sla.block_diag(L1, L2))
+
+
+def test_identity_padding_invariant():
+    """chol(diag(A, I)) = diag(chol(A), I) exactly; the padding rule for ragged tiles."""
+    X, _ = gp_inputs.gp_problem(37, seed=3)
+    A = oracle.gp_assemble(X, 1.0, 1.0, 0.1)
+    L, _ = oracle.cholesky(A)
+    Lp, info = oracle.cholesky(sla.block_diag(A, np.eye(11)))
+    assert info == 0
+    np.testing.assert_array_equal(Lp, sla.block_diag(L, np.eye(11)))
+
+
+@pytest.mark.parametrize("n,family", [(64, "dense-int"), (200, "dense-int"), (300, "sparse-dd"),
+                                      (257, "small-int")])
+def test_known_l0_exact_recovery(n, family):
+    L0, A = gp_inputs.known_l0(n, family, seed=n)
+    L, info = oracle.cholesky(A)
+    assert info == 0
+    np.testing.assert_array_equal(L, L0)
+
+
+@pytest.mark.parametrize("n,family", [(120, "dense-int"), (300, "sparse-dd")])
+def test_known_l0_exact_solve(n, family):
+    L0, A = gp_inputs.known_l0(n, family, seed=7)
+    rng = np.random.default_rng(5)
+    x0 = rng.integers(-4, 5, size=(n, 3)).astype(np.int64)
+    b = (A.astype(np.int64) @ x0).astype(np.float64)
+    y = oracle.forward(L0, b)
+    np.testing.assert_array_equal(y, (L0.T.astype(np.int64) @ x0).astype(np.float64))
+    x = oracle.backward(L0, y)
+    np.testing.assert_array_equal(x, x0.astype(np.float64))
+
+
+@pytest.mark.parametrize("n", [3, 8, 15])
+def test_mpmath_brute_force(n):
+    """50-digit mpmath Cholesky and solve; FP64 oracle within c * kappa * u."""
+    X, B = gp_inputs.gp_problem(n, seed=11 + n, k=1)
+    A = oracle.gp_assemble(X, 0.8, 1.0, 0.05)
+    mpmath.mp.dps = 50
+    Am = mpmath.matrix(A.tolist())
+    Lm = mpmath.cholesky(Am)
+    xm = mpmath.cholesky_solve(Am, mpmath.matrix(B[:, 0].tolist()))
+    L, info = oracle.cholesky(A)
+    assert info == 0
+    Lref = np.array(Lm.tolist(), dtype=np.float64)
+    kappa = np.linalg.cond(A)
+    np.testing.assert_allclose(L, Lref, rtol=0, atol=50 * n * kappa * U * np.abs(Lref).max())
+    x = oracle.solve(L, B[:, 0])
+    xref = np.array([float(v) for v in xm])
+    assert np.linalg.norm(x - xref) / np.linalg.norm(xref) <= 10 * n * kappa * U
+
+
+def test_against_lapack_on_gp_matrix():
+    X, _ = gp_inputs.gp_problem(300, seed=4)
+    A = oracle.gp_assemble(X, 1.0, 1.0, 0.1)
+    L, info = oracle.cholesky(A)
+    assert info == 0
+    Lnp = np.linalg.cholesky(A)
+    kappa = np.linalg.cond(A)
+    assert np.linalg.norm(L - Lnp) / np.linalg.norm(Lnp) <= 300 * kappa * U
+    be = oracle.backward_error(A, L)
+    assert be <= 1e-15
+
+
+def test_triangular_solves_against_scipy():
+    X, B = gp_inputs.gp_problem(150, seed=9, k=4)
+    A = oracle.gp_assemble(X, 1.0, 1.0, 0.1)
+    L, _ = oracle.cholesky(A)
+    y = oracle.forward(L, B)
+    np.testing.assert_allclose(y, sla.solve_triangular(L, B, lower=True), rtol=1e-12, atol=1e-12)
+    x = oracle.backward(L, y)
+    np.testing.assert_allclose(x, sla.solve_triangular(L.T, y, lower=False), rtol=1e-12, atol=1e-12)
+    xs = oracle.solve(L, B)
+    xnp = np.linalg.solve(A, B)
+    assert np.linalg.norm(xs - xnp) / np.linalg.norm(xnp) <= 1e-12
+
+
+# -------------------------------------------------------------- assembly ---
+
+def test_gp_assemble_against_sklearn_rbf():
+    from sklearn.gaussian_process.kernels import RBF
+    X, _ = gp_inputs.gp_problem(200, d=8, seed=1)
+    for ls, var, noise in [(1.0, 1.0, 0.1), (0.5, 1.0, 1.0), (2.0, 3.0, 0.01)]:
+        A = oracle.gp_assemble(X, ls, var, noise)
+        K = var * RBF(length_scale=ls)(X) + noise * np.eye(200)
+        np.testing.assert_allclose(A, K, rtol=1e-13, atol=0)
+        assert np.array_equal(A, A.T)
+        assert np.all(np.diag(A) == var + noise)
+        off = A[~np.eye(200, dtype=bool)]
+        assert np.all(off > 0) and np.all(off <= var)
+
+
+def test_gp_assemble_closed_form_points():
+    """Points at squared distance 2 ls^2 ln 2 and 2 ls^2 give var/2 and var/e."""
+    ls = 0.7
+    X = np.zeros((3, 8))
+    X[1, 0] = ls * np.sqrt(2 * np.log(2.0))
+    X[2, 3] = ls * np.sqrt(2.0)
+    A = oracle.gp_assemble(X, ls, 2.0, 0.25)
+    assert A[0, 0] == 2.25
+    np.testing.assert_allclose(A[1, 0], 1.0, rtol=8 * U)
+    np.testing.assert_allclose(A[2, 0], 2.0 / np.e, rtol=8 * U)
+    assert oracle.gp_entry(X, 2, 0, ls, 2.0, 0.25) == A[2, 0]
+    assert oracle.gp_entry(X, 1, 1, ls, 2.0, 0.25) == 2.25
+
+
+def test_gp_lambda_min_bound():
+    """lambda_min(A) >= noise: the certificate's premise."""
+    X, _ = gp_inputs.gp_problem(400, seed=6)
+    A = oracle.gp_assemble(X, 2.0, 1.0, 0.01)
+    assert np.linalg.eigvalsh(A).min() >= 0.01 * (1 - 1e-8)
+
+
+# ------------------------------------------------------ residual / refine ---
+
+def test_residual_exact_on_integers():
+    L0, A = gp_inputs.known_l0(90, "sparse-dd", seed=2)
+    rng = np.random.default_rng(1)
+    x = rng.integers(-5, 6, size=(90, 2)).astype(np.float64)
+    b = A @ x
+    r = oracle.residual(A, x, b)
+    assert np.all(r == 0)
+    x2 = x.copy()
+    x2[3, 1] += 1.0
+    r = oracle.residual(A, x2, b)
+    np.testing.assert_array_equal(r[:, 1], -A[:, 3])
+
+
+def test_gp_residual_matches_assembled():
+    X, B = gp_inputs.gp_problem(120, seed=8, k=2)
+    A = oracle.gp_assemble(X, 0.9, 1.0, 0.2)
+    xs = np.random.default_rng(3).standard_normal((120, 2))
+    r1 = oracle.residual(A, xs, B)
+    r2 = oracle.gp_residual(X, 0.9, 1.0, 0.2, xs, B)
+    np.testing.assert_allclose(r1, r2, rtol=0, atol=1e-13)
+    np.testing.assert_allclose(r1, B - A @ xs, rtol=0, atol=1e-12)
+
+
+@pytest.mark.parametrize("method", ["ir", "pcg"])
+def test_refinement_with_fp32_factor(method):
+    n = 400
+    X, B = gp_inputs.gp_problem(n, seed=12, k=3)
+    A = oracle.gp_assemble(X, 1.0, 1.0, 0.1)
+    L, _ = oracle.cholesky(A)
+    F = L.astype(np.float32).astype(np.float64)  # emulated low-precision factor
+    xnp = np.linalg.solve(A, B)
+    if method == "ir":
+        Xs, it, cert, failed = oracle.refine(F, A, B, lam=0.1, tol=1e-10)
+    else:
+        Xs, it, cert, failed = oracle.pcg(F, A, B, lam=0.1, tol=1e-10)
+    assert failed == 0
+    assert np.all(cert <= 0.5e-10)
+    assert np.all(it >= 1)  # the FP32 factor alone is not accurate enough
+    for c in range(3):
+        err = np.linalg.norm(Xs[:, c] - xnp[:, c]) / np.linalg.norm(xnp[:, c])
+        assert err <= 1e-10
+        # the certificate is a rigorous bound on the error
+        assert err <= cert[c] * np.linalg.norm(Xs[:, c]) / np.linalg.norm(xnp[:, c]) * (1 + 1e-6) + 1e-15
+
+
+def test_refinement_without_noise_bound():
+    n = 200
+    X, B = gp_inputs.gp_problem(n, seed=13, k=1)
+    A = oracle.gp_assemble(X, 1.0, 1.0, 0.1)
+    L, _ = oracle.cholesky(A)
+    F = L.astype(np.float32).astype(np.float64)
+    Xs, it, cert, failed = oracle.refine(F, A, B, lam=0.0, tol=1e-12)
+    assert failed == 0
+    xnp = np.linalg.solve(A, B)
+    assert np.linalg.norm(Xs - xnp) / np.linalg.norm(xnp) <= 1e-11
+
+
+def test_certificate_matches_definition_cases():
+    r = np.array([3.0, 4.0])
+    x = np.array([0.0, 10.0])
+    assert oracle.certificate(r, x, 0.5) == 1.0
+
+
+def test_backward_error_exact_factor_is_zero():
+    L0, A = gp_inputs.known_l0(60, "dense-int", seed=3)
+    assert oracle.backward_error(A, L0) == 0.0
+    L1 = L0.copy()
+    L1[10, 3] += 1.0
+    E = A - L1 @ L1.T
+    np.testing.assert_allclose(oracle.backward_error(A, L1), np.linalg.norm(E) / np.linalg.norm(A), rtol=1e-12)
+
+
+def test_inputs_are_seeded():
+    X1, B1 = gp_inputs.gp_problem(50, seed=4, k=2)
+    X2, B2 = gp_inputs.gp_problem(50, seed=4, k=2)
+    assert np.array_equal(X1, X2) and np.array_equal(B1, B2)
+    assert X1.flags.c_contiguous and B1.flags.f_contiguous
+    assert X1.min() >= -1 and X1.max() < 1
+    s = gp_inputs.serving_stream(duration_s=2.0, seed=0)
+    assert len(s) > 100 and all(256 <= r.n <= 8192 and 1 <= r.k <= 64 for r in s)
+    assert all(a.arrival < b.arrival for a, b in zip(s, s[1:]))
