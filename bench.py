@@ -1,0 +1,253 @@
+#!/usr/bin/env python3
+"""Benchmark of the GP Cholesky solver path on one MI355X.
+
+Default workload (one "step" = one pass of the whole FP64 hot path over one
+synthetic GP problem, inputs resident in HBM before timing starts):
+  gp_assemble (SE kernel, n = 32768, d = 8, lengthscale 1, variance 1,
+  noise 0.1, seed 0)  ->  chol_factor (FP64, tile 128)  ->  chol_solve with
+  1 right-hand side  ->  chol_solve with 16 right-hand sides.
+``value`` is n^3/3 flops per step divided by the whole step time (GFLOP/s);
+``factor_gflops`` is n^3/3 over the factorisation alone.
+
+Other workloads (``--workload``) print the same kind of JSON line:
+  fp64_n1024    the small latency case (tile 128), p50/p99 over many steps;
+  mixed_n65536  FP64 vs FP32-factor + refinement, time to a certified 1e-10
+                solution of one right-hand side;
+  fp64_n65536   the FP64 factorisation at n = 65536.
+
+The roofline object is measured live: every trailing-update launch (the
+dominant kernel) is bracketed by HIP events on the stream it runs on, and
+its algorithmic flop count is summed (chol_profile_read).  cpu_baseline
+times the CPU oracle (assembly + Cholesky + solve) on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Cholesky GFLOP/s (n^3/3) + time-to-1e-10 solve, FP64 vs mixed; p50/p99 latency"
+FP64_PEAK_TFLOPS = 78.6   # MI355X dense FP64 matrix peak
+FP32_PEAK_TFLOPS = 157.3  # MI355X dense FP32 matrix peak
+HP = (1.0, 1.0, 0.1)      # lengthscale, variance, noise
+
+
+def percentile(xs, q):
+    return float(np.percentile(np.asarray(xs, dtype=np.float64), q)) if len(xs) else None
+
+
+def cpu_baseline(n: int):
+    """Oracle pipeline (assembly + Cholesky-Crout + forward/back substitution) on the host."""
+    import gp_inputs
+    import oracle
+    X, B = gp_inputs.gp_problem(n, d=8, k=1, seed=0)
+    oracle.build()
+    t0 = time.perf_counter()
+    A = oracle.gp_assemble(X, *HP)
+    L, info = oracle.cholesky(A)
+    oracle.solve(L, B)
+    dt = time.perf_counter() - t0
+    assert info == 0
+    return {"value": round(n ** 3 / 3 / dt / 1e9, 3), "unit": "GFLOP/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": f"oracle gp_assemble + Cholesky-Crout + solve (k=1) at n={n}, SE d=8, "
+                      f"ls=1 var=1 noise=0.1, seed 0: {dt:.2f} s; GFLOP/s = n^3/3 / time"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="fp64_n32768",
+                    choices=["fp64_n32768", "fp64_n1024", "fp64_n65536", "mixed_n65536"])
+    ap.add_argument("--n", type=int, default=0, help="override the order")
+    ap.add_argument("--tile", type=int, default=128)
+    ap.add_argument("--panel-width", type=int, default=0)
+    ap.add_argument("--lookahead", type=int, default=-1)
+    ap.add_argument("--super-tile", type=int, default=0)
+    ap.add_argument("--cpu-n", type=int, default=8192)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-profile", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
+                                   "(multi-GPU sharding is a design note, not implemented)"}))
+        sys.exit(2)
+
+    import torch
+    import gp_inputs
+    import paper_2605_13209_amd as P
+
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU visible"}))
+        sys.exit(1)
+    torch.cuda.set_device(0)
+    if args.panel_width:
+        P.set_option("panel_width", args.panel_width)
+    if args.lookahead >= 0:
+        P.set_option("lookahead", args.lookahead)
+    if args.super_tile:
+        P.set_option("super_tile", args.super_tile)
+
+    wl = args.workload
+    n = args.n or {"fp64_n32768": 32768, "fp64_n1024": 1024, "fp64_n65536": 65536, "mixed_n65536": 65536}[wl]
+    tile = args.tile
+    steps, warmup = args.steps, args.warmup
+    if wl == "fp64_n1024" and steps == 5:
+        steps, warmup = 100, 5
+
+    X_np, B_np = gp_inputs.gp_problem(n, d=8, k=16, seed=0)
+    Xd = torch.from_numpy(X_np).cuda()
+    B16_src = P.to_colmajor(torch.from_numpy(B_np))
+    B1_src = B16_src[:, :1]
+    A = P.colmajor_empty(n, n)
+    extra = {}
+
+    if wl.startswith("fp64"):
+        ws = torch.empty(P.chol_factor_bytes(n, "fp64", tile), dtype=torch.uint8, device="cuda")
+        b1 = P.colmajor_empty(n, 1)
+        b16 = P.colmajor_empty(n, 16)
+        with_16 = wl != "fp64_n65536"
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
+
+        def step():
+            ev[0].record()
+            P.gp_assemble(Xd, *HP, full=False, out=A)
+            ev[1].record()
+            F = P.chol_factor(A, "fp64", tile, workspace=ws, sync=False)
+            ev[2].record()
+            b1.copy_(B1_src)
+            P.chol_solve(F, b1)
+            ev[3].record()
+            if with_16:
+                b16.copy_(B16_src)
+                P.chol_solve(F, b16)
+            ev[4].record()
+            return F
+
+        for _ in range(warmup):
+            F = step()
+        torch.cuda.synchronize()
+        if F.info() != 0:
+            raise RuntimeError(f"factorisation failed, info={F.info()}")
+        P.chol_profile_reset()
+        if not args.no_profile:
+            P.set_option("profile", 1)
+        t_step, t_asm, t_fac, t_s1, t_s16 = [], [], [], [], []
+        torch.cuda.synchronize()
+        wall0 = time.perf_counter()
+        for _ in range(steps):
+            F = step()
+            ev[4].synchronize()
+            t_asm.append(ev[0].elapsed_time(ev[1]))
+            t_fac.append(ev[1].elapsed_time(ev[2]))
+            t_s1.append(ev[2].elapsed_time(ev[3]))
+            t_s16.append(ev[3].elapsed_time(ev[4]))
+            t_step.append(ev[0].elapsed_time(ev[4]))
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - wall0
+        P.set_option("profile", 0)
+        info = F.info()
+        if info != 0:
+            raise RuntimeError(f"factorisation failed, info={info}")
+        # certificate of the k=1 solve: ||b - A x|| / (noise ||x||) bounds the relative error
+        R = P.chol_residual(A, b1, B1_src)
+        cert = float(torch.linalg.norm(R) / (HP[2] * torch.linalg.norm(b1)))
+        flops = n ** 3 / 3
+        ms_step = float(np.mean(t_step))
+        value = flops / (ms_step * 1e-3) / 1e9
+        extra.update({
+            "factor_gflops": round(flops / (np.mean(t_fac) * 1e-3) / 1e9, 1),
+            "factor_frac_fp64_peak": round(flops / (np.mean(t_fac) * 1e-3) / (FP64_PEAK_TFLOPS * 1e12), 4),
+            "ms": {"assemble": round(float(np.mean(t_asm)), 3), "factor": round(float(np.mean(t_fac)), 3),
+                   "solve_k1": round(float(np.mean(t_s1)), 3),
+                   "solve_k16": round(float(np.mean(t_s16)), 3) if with_16 else None},
+            "p50_ms": round(percentile(t_step, 50), 3), "p99_ms": round(percentile(t_step, 99), 3),
+            "factor_p50_ms": round(percentile(t_fac, 50), 3), "factor_p99_ms": round(percentile(t_fac, 99), 3),
+            "solve_cert_k1": cert, "wall_s": round(wall, 3),
+            "solve_k1_gbps": round(chol_bytes(n, tile, 8) * 2 / (np.mean(t_s1) * 1e-3) / 1e9, 1),
+        })
+        dtype = "f64"
+        peak = FP64_PEAK_TFLOPS
+        config = {"workload": f"fp64_cholesky_solve_n{n}", "n": n, "tile": tile,
+                  "panel_width": P.get_option("panel_width"), "lookahead": P.get_option("lookahead"),
+                  "rhs": [1, 16] if with_16 else [1], "kernel": "SE d=8 lengthscale=1 variance=1 noise=0.1",
+                  "seed": 0, "precision": "fp64"}
+    else:  # mixed_n65536: time to a certified 1e-10 solution, FP64 vs FP32 + IR / PCG
+        P.gp_assemble(Xd, *HP, full=False, out=A)
+        res = {}
+        b = P.colmajor_empty(n, 1)
+        for prec, method in (("fp64", "ir"), ("fp32", "ir"), ("fp32", "pcg")):
+            ws = torch.empty(P.chol_factor_bytes(n, prec, tile), dtype=torch.uint8, device="cuda")
+            ts, tf, it, ce = [], [], [], []
+            for rep in range(warmup + steps):
+                torch.cuda.synchronize()
+                if rep == warmup and not args.no_profile and prec == "fp32" and method == "ir":
+                    P.chol_profile_reset()
+                    P.set_option("profile", 1)
+                t0 = time.perf_counter()
+                F = P.chol_factor(A, prec, tile, workspace=ws, sync=False)
+                r = P.chol_refine_solve(F, B1_src, A=A, noise=HP[2], tol=1e-10, method=method, out=b)
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                if rep >= warmup:
+                    ts.append((t1 - t0) * 1e3)
+                    tf.append((t1 - t0) * 1e3 - r.time_ms)
+                    it.append(r.iters)
+                    ce.append(r.cert)
+                del F
+            if prec == "fp32" and method == "ir":
+                P.set_option("profile", 0)
+            res[f"{prec}_{method}"] = {"time_to_solution_ms": round(float(np.mean(ts)), 2),
+                                       "factor_ms": round(float(np.mean(tf)), 2),
+                                       "iters": int(max(it)), "cert": float(max(ce)),
+                                       "p50_ms": round(percentile(ts, 50), 2), "p99_ms": round(percentile(ts, 99), 2)}
+            del ws
+            torch.cuda.empty_cache()
+        flops = n ** 3 / 3
+        best_mixed = min(res["fp32_ir"]["time_to_solution_ms"], res["fp32_pcg"]["time_to_solution_ms"])
+        ms_step = best_mixed
+        value = flops / (res["fp32_ir"]["factor_ms"] * 1e-3) / 1e9
+        extra.update({"solutions": res,
+                      "speedup_mixed_vs_fp64": round(res["fp64_ir"]["time_to_solution_ms"] / best_mixed, 3)})
+        dtype = "f32"
+        peak = FP32_PEAK_TFLOPS
+        config = {"workload": f"mixed_fp32_ir_n{n}", "n": n, "tile": tile, "rhs": [1],
+                  "kernel": "SE d=8 lengthscale=1 variance=1 noise=0.1", "seed": 0, "tol": 1e-10}
+
+    roofline = None
+    kms, kl, kfl = P.chol_profile_read()
+    if kl > 0 and kms > 0:
+        ach = kfl / (kms * 1e-3) / 1e12
+        roofline = {"bound": "mfma", "achieved": round(ach, 3), "peak": peak, "unit": "TFLOP/s",
+                    "frac": round(ach / peak, 4), "traffic": None,
+                    "kernel": "update_kernel (Step-3 trailing update)", "launches": kl,
+                    "avg_launch_us": round(kms * 1e3 / kl, 2),
+                    "avg_launch_gflop": round(kfl / kl / 1e9, 4)}
+
+    out = {"metric": METRIC, "value": round(value, 2), "unit": "GFLOP/s", "n_gpus": 1, "steps": steps,
+           "warmup": warmup, "ms_per_step": round(ms_step, 3), "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": dtype, "data": "synthetic", "config": config,
+           "roofline": roofline}
+    out.update(extra)
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(args.cpu_n)
+    print(json.dumps(out), flush=True)
+
+
+def chol_bytes(n, tile, es):
+    N = (n + tile - 1) // tile
+    return N * (N + 1) // 2 * tile * tile * es
+
+
+if __name__ == "__main__":
+    main()

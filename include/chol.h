@@ -1,0 +1,231 @@
+/*
+ * chol.h - C ABI of the MI355X (gfx950) dense SPD / Gaussian-process solver.
+ *
+ * The library solves A x = b for a symmetric positive definite A (the
+ * problem statement of the paper, Introduction and Fundamentals) through the
+ * blocked right-looking Cholesky factorisation A = L L^T, L lower triangular
+ * (Fundamentals, "The Cholesky decomposition", and the blocked algorithm in
+ * the paper's first algorithm figure, right column: Step 1 factors the
+ * diagonal block, Step 2 solves the panel below it, Step 3 updates the
+ * trailing blocks), followed by forward and back substitution with L.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Matrices are column-major: element (i, j) of a matrix with leading
+ *   dimension ld sits at M[i + j*ld].  Only the lower triangle of A is read.
+ * - Pointers named A, B, X, L, workspace are DEVICE pointers (HBM of the
+ *   current HIP device) unless stated otherwise.  `stream` is a hipStream_t
+ *   passed as void*; NULL means the default stream.  Calls are stream-ordered
+ *   and return after enqueueing, unless stated otherwise.
+ * - Ownership: the caller allocates and frees all device memory.  The library
+ *   never allocates device memory; it owns only the small host handle
+ *   returned by chol_factor, plus one side stream and a few events per device
+ *   that it creates on first use and keeps until the process ends.
+ * - Return value: CHOL_OK (0) on success; -i when argument i (1-based) is
+ *   invalid; one of the negative CHOL_ERR_* codes otherwise.  Nothing is
+ *   enqueued when an argument is rejected.
+ * - Not positive definite: *info = j + 1 where j is the first (0-based) global
+ *   column whose pivot is not positive (or is NaN), exactly as LAPACK's
+ *   potrf reports it.  The factor contents are then unspecified.
+ */
+#ifndef CHOL_MI355X_H
+#define CHOL_MI355X_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---------------------------------------------------- */
+#define CHOL_OK 0
+#define CHOL_ERR_HIP (-100)           /* a HIP runtime call failed            */
+#define CHOL_ERR_WORKSPACE (-101)     /* workspace smaller than required      */
+#define CHOL_ERR_NOT_CONVERGED (-102) /* refinement hit max_iter              */
+#define CHOL_ERR_NOT_SPD (-103)       /* factor failed (info > 0)             */
+#define CHOL_ERR_UNSUPPORTED (-104)   /* precision / tile not built           */
+#define CHOL_ERR_BAD_HANDLE (-105)
+
+/* ---- precisions of the factor ---------------------------------------- */
+/* CHOL_FP64        : FP64 storage, FP64 MFMA trailing update.
+ * CHOL_FP32        : FP32 storage, FP32 MFMA trailing update; the
+ *                    diagonal-block factorisation and the panel solves
+ *                    compute in FP64 and round their result to FP32.
+ * CHOL_FP16_SCALED : FP32 storage of H = A / s (s = the largest diagonal
+ *                    entry), trailing update with FP16 operands and FP32
+ *                    accumulation; diagonal blocks and panel solves in FP64.
+ *                    For matrices with a constant diagonal (every SE kernel
+ *                    matrix) H has unit diagonal, so all |L_H| <= 1.
+ * The two low-precision forms are meant to be followed by chol_refine_solve,
+ * which recovers FP64 accuracy (the paper names mixed precision as future
+ * work in its Conclusion).                                                  */
+#define CHOL_FP64 0
+#define CHOL_FP32 1
+#define CHOL_FP16_SCALED 2
+
+#define CHOL_REFINE_IR 0  /* iterative refinement                          */
+#define CHOL_REFINE_PCG 1 /* CG preconditioned with M = L L^T (the paper's
+                             CG algorithm, first algorithm figure, left
+                             column, with the factor as preconditioner)      */
+
+typedef struct chol_factor_s *chol_handle;
+
+typedef struct {
+  int32_t iters;          /* corrections (IR) or iterations (PCG), max over RHS */
+  int32_t converged;      /* 1 if every RHS met the stopping rule              */
+  double cert;            /* max over RHS of the final error bound (see below) */
+  double resid_norm;      /* max over RHS of ||b - A x||_2 at exit             */
+  double time_ms;         /* host wall time of the call, including its sync    */
+} chol_refine_report;
+
+/* ---- gp_assemble ------------------------------------------------------
+ * Squared-exponential Gaussian-process covariance plus noise, the synthetic
+ * stand-in for the paper's GP kernel matrices (Results, Experimental Setup):
+ *   A_ij = variance * exp(-|x_i - x_j|^2 / (2 lengthscale^2))   (i != j)
+ *   A_ii = variance + noise
+ * X  : device, n x d row-major features, row stride ldx (>= d), FP64.
+ * A  : device, n x n column-major FP64, leading dimension lda (>= n).
+ * uplo_full = 0 writes the lower triangle only (upper untouched); 1 writes
+ * the full symmetric matrix (bitwise symmetric).
+ * Errors: -2 n < 0, -3 d < 1, -4 ldx < d, -5/-6/-7 non-positive lengthscale,
+ * negative variance or noise, -9 lda < max(1, n).                        */
+int gp_assemble(const double *X, int64_t n, int64_t d, int64_t ldx,
+                double lengthscale, double variance, double noise, double *A,
+                int64_t lda, int uplo_full, void *stream);
+
+/* ---- chol_factor_bytes -------------------------------------------------
+ * Device workspace, in bytes, that chol_factor needs for an order-n matrix
+ * at the given precision and tile (tile 0 = the tuned default).  The factor
+ * is stored as the paper stores it (Implementation section): only the
+ * lower-triangular and diagonal square blocks, each block contiguous.
+ * Returns 0 for invalid arguments.  Host-only; no device work.           */
+size_t chol_factor_bytes(int64_t n, int precision, int tile);
+
+/* ---- chol_tile_default -------------------------------------------------
+ * The tile chol_factor uses when called with tile = 0.                   */
+int chol_tile_default(int64_t n, int precision);
+
+/* ---- chol_factor -------------------------------------------------------
+ * Factor A = L L^T (blocked right-looking, Steps 1-3 of the paper's
+ * algorithm) into the workspace.
+ * A         : device, n x n column-major FP64 (lower triangle read), lda.
+ *             Not modified.
+ * precision : CHOL_FP64 / CHOL_FP32 / CHOL_FP16_SCALED.
+ * tile      : block side 64 or 128; 0 selects chol_tile_default.
+ * workspace : device, >= chol_factor_bytes(n, precision, tile) bytes,
+ *             256-byte aligned.  Holds the factor; must stay allocated and
+ *             untouched while the handle is used.
+ * F         : out, host handle of type chol_handle (free with
+ *             chol_factor_free).
+ * info      : out, may be NULL.  If non-NULL the call synchronises the stream
+ *             and stores the LAPACK-style info (0 = success).  If NULL the
+ *             call is fully asynchronous; use chol_get_info later.
+ * Errors: -2 n < 0, -3 lda < max(1,n), -4 precision, -5 tile, -6 workspace
+ * NULL or misaligned, -7 ws_bytes too small (also CHOL_ERR_WORKSPACE), -8 F
+ * NULL.                                                                  */
+int chol_factor(const double *A, int64_t n, int64_t lda, int precision,
+                int tile, void *workspace, size_t ws_bytes, chol_handle *F,
+                int64_t *info, void *stream);
+
+/* Synchronises the factor's stream and reports info (0 = success).       */
+int chol_get_info(chol_handle F, int64_t *info);
+
+/* ---- chol_solve --------------------------------------------------------
+ * B <- A^{-1} B using the factor only: forward substitution L Y = B, then
+ * back substitution L^T X = Y (Fundamentals, "The Cholesky decomposition").
+ * Arithmetic is FP64 whatever the factor's storage precision.
+ * B : device, n x nrhs column-major FP64, ldb >= max(1, n), overwritten.
+ * Errors: CHOL_ERR_BAD_HANDLE, -2 B NULL with nrhs > 0, -3 nrhs < 0,
+ * -4 ldb, CHOL_ERR_NOT_SPD if the factorisation reported info > 0.       */
+int chol_solve(chol_handle F, double *B, int64_t nrhs, int64_t ldb,
+               void *stream);
+
+/* ---- chol_refine_bytes -------------------------------------------------
+ * Device workspace chol_refine_solve needs for nrhs right-hand sides.    */
+size_t chol_refine_bytes(int64_t n, int64_t nrhs, int method);
+
+/* ---- chol_refine_solve -------------------------------------------------
+ * Solve A X = B to FP64 accuracy with a (typically low-precision) factor F
+ * of A, by iterative refinement (method CHOL_REFINE_IR) or by CG
+ * preconditioned with M = F F^T (CHOL_REFINE_PCG).  Residuals r = b - A x
+ * and the solution updates are computed in FP64.
+ * A      : device, FP64 n x n column-major (lower triangle read), lda; or
+ *          NULL, in which case the residual is computed matrix-free from the
+ *          GP features Xf (n x d row-major, ldxf) and the hyper-parameters,
+ *          with exactly the formula of gp_assemble.
+ * noise  : lower bound lam on the smallest eigenvalue of A (for a GP
+ *          matrix: the noise variance).  With lam > 0 the stopping rule is
+ *          the certificate ||r||_2 / (lam ||x||_2) <= tol / 2, a rigorous
+ *          bound on the relative error ||x - x*|| / ||x||.  With lam <= 0 it
+ *          is ||d||_2 <= tol ||x||_2 for the last correction d.
+ * B      : device, n x nrhs column-major FP64, ldb.  Not modified.
+ * X      : device, n x nrhs column-major FP64, ldxs.  Output.
+ * workspace: device, >= chol_refine_bytes(n, nrhs, method) bytes.
+ * rep    : out (host), may be NULL.
+ * The call synchronises the stream once per iteration (it reads back one
+ * norm per right-hand side).  Returns CHOL_ERR_NOT_CONVERGED if max_iter
+ * is reached; X then holds the last iterate.                             */
+int chol_refine_solve(chol_handle F, const double *A, int64_t lda,
+                      const double *Xf, int64_t d, int64_t ldxf,
+                      double lengthscale, double variance, double noise,
+                      const double *B, int64_t ldb, double *X, int64_t ldxs,
+                      int64_t nrhs, double tol, int max_iter, int method,
+                      void *workspace, size_t ws_bytes,
+                      chol_refine_report *rep, void *stream);
+
+/* ---- chol_residual -----------------------------------------------------
+ * R = B - A X in FP64 with A symmetric given by its lower triangle (lda),
+ * all n x nrhs column-major device arrays.  Deterministic (no atomics).   */
+int chol_residual(const double *A, int64_t lda, int64_t n, const double *X,
+                  int64_t ldx, const double *B, int64_t ldb, double *R,
+                  int64_t ldr, int64_t nrhs, void *stream);
+
+/* ---- chol_factor_to_dense ----------------------------------------------
+ * Write the factor as a dense n x n column-major FP64 matrix L (ldl): the
+ * lower triangle holds L (widened from the storage precision and, for
+ * CHOL_FP16_SCALED, multiplied back by sqrt(s) so that L L^T ~ A); the
+ * strict upper triangle is set to zero.                                  */
+int chol_factor_to_dense(chol_handle F, double *L, int64_t ldl, void *stream);
+
+/* Host handle queries.  Values are fixed when chol_factor returns.        */
+int64_t chol_factor_n(chol_handle F);
+int chol_factor_tile(chol_handle F);
+int chol_factor_precision(chol_handle F);
+
+/* Frees the host handle only; the workspace stays the caller's.           */
+void chol_factor_free(chol_handle F);
+
+/* Human-readable text for a status code (static storage).                 */
+const char *chol_status_string(int status);
+
+/* ---- kernel timing ------------------------------------------------------
+ * With option "profile" = 1, every launch of the Step-3 trailing-update
+ * kernel is bracketed by a pair of HIP events recorded on the stream it is
+ * launched on, and the launch's algorithmic flop count is accumulated
+ * (2 b^2 K per off-diagonal tile and b (b + 1) K per diagonal tile, K the
+ * inner dimension of the launch).  chol_profile_read waits for the recorded
+ * events and returns the summed kernel time (ms), the number of launches and
+ * the summed flops; chol_profile_reset forgets everything recorded.  Not
+ * thread-safe; meant for benchmarks.                                       */
+int chol_profile_read(double *ms, int64_t *launches, double *flops);
+void chol_profile_reset(void);
+
+/* ---- tuning knobs (process-wide; set before factorising) ---------------
+ * "panel_width"  : tiles per outer step whose Step-3 update is applied in
+ *                  one pass (1..8, default 2).
+ * "lookahead"    : 1 overlaps the next panel's Steps 1-2 with the current
+ *                  trailing update on a second stream (default 1).
+ * "super_tile"   : side, in tiles, of the groups the trailing-update grid
+ *                  walks through together for cache reuse (default 8).
+ * "graph"        : 1 replays a captured HIP graph of the factorisation for
+ *                  repeated (n, tile, precision) calls (default 0).
+ * "profile"      : 1 records kernel timing (see chol_profile_read).
+ * Returns CHOL_OK or -1 (unknown key) / -2 (value out of range).         */
+int chol_set_option(const char *key, int64_t value);
+int64_t chol_get_option(const char *key);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CHOL_MI355X_H */

@@ -75,6 +75,7 @@ def _load():
         lib.oracle_backward_error.restype = ctypes.c_double
         lib.oracle_certificate.argtypes = [_D, _D, _I, ctypes.c_double]
         lib.oracle_certificate.restype = ctypes.c_double
+        lib.oracle_num_threads.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -88,6 +89,11 @@ def _colmajor(a) -> np.ndarray:
     if a.ndim == 1:
         a = a[:, None]
     return np.array(a, dtype=np.float64, order="F", copy=True)
+
+
+def num_threads() -> int:
+    """Threads used by the oracle's OpenMP loops."""
+    return int(_load().oracle_num_threads())
 
 
 def gp_assemble(X, lengthscale: float, variance: float, noise: float) -> np.ndarray:

@@ -1,0 +1,205 @@
+// FP64 vector kernels of the refinement loop: the residual R = B - A X for a
+// symmetric A given by its lower triangle (the refinement counterpart of the
+// paper's CG residual b - A x, first algorithm figure, left column), column
+// dot products, and axpby updates.  All are HBM-bound and deterministic
+// (fixed work assignment and reduction order, no atomics).
+#include "internal.hpp"
+
+namespace chol {
+namespace {
+
+__device__ inline void two_sum(double a, double b, double &s, double &e) {
+  s = a + b;
+  const double bb = s - a;
+  e = (a - (s - bb)) + (b - bb);
+}
+
+// Residual.  grid (ceil(n/64), ceil(nrhs/NR)); block 256.  Bm == nullptr
+// means B = 0, i.e. R = -A X (the product used by the CG iteration).  A workgroup owns
+// 64 rows and walks every 64-column block of the symmetric matrix: blocks
+// left of the diagonal come from the lower triangle as stored, blocks right
+// of it from the lower triangle transposed (both read along columns, so the
+// HBM reads are contiguous), each staged through LDS.  Lane o of the four
+// waves accumulates row o over a quarter of the block's columns in
+// double-double (TwoProd by fma, TwoSum), so the residual's own rounding is
+// far below FP64 round-off of |A||x| even at n ~ 1e5.
+template <int NR>
+__global__ __launch_bounds__(256) void symm_residual_kernel(
+    const double *__restrict__ A, int64_t lda, int64_t n, const double *__restrict__ X,
+    int64_t ldx, const double *__restrict__ Bm, int64_t ldb, double *__restrict__ R, int64_t ldr,
+    int64_t nrhs) {
+  constexpr int P = 65;
+  __shared__ double at[64 * P];   // at[jj * P + ii] = A(I0 + ii, J0 + jj)
+  __shared__ double xs[64 * NR];  // xs[jj * NR + cc]
+  __shared__ double red_s[4 * 64 * NR], red_e[4 * 64 * NR];
+  const int tid = threadIdx.x, o = tid & 63, h = tid >> 6;
+  const int64_t I0 = (int64_t)blockIdx.x * 64;
+  const int64_t c0 = (int64_t)blockIdx.y * NR;
+  const int nc = (int)min<int64_t>(NR, nrhs - c0);
+  double hs[NR], he[NR];
+#pragma unroll
+  for (int cc = 0; cc < NR; ++cc) hs[cc] = he[cc] = 0.0;
+  const int64_t nb = (n + 63) / 64;
+  for (int64_t Jb = 0; Jb < nb; ++Jb) {
+    const int64_t J0 = Jb * 64;
+    __syncthreads();
+    for (int e = tid; e < 64 * 64; e += 256) {
+      const int a = e & 63, bc = e >> 6;  // a: contiguous index in memory
+      if (J0 < I0) {  // lower block: value A(I0+a, J0+bc) stored at column J0+bc
+        const int64_t gi = I0 + a, gj = J0 + bc;
+        at[bc * P + a] = (gi < n && gj < n) ? A[gi + gj * lda] : 0.0;
+      } else if (J0 > I0) {  // upper block: A(I0+bc, J0+a) = stored A(J0+a, I0+bc)
+        const int64_t gi = I0 + bc, gj = J0 + a;
+        at[a * P + bc] = (gi < n && gj < n) ? A[gj + gi * lda] : 0.0;
+      } else if (a >= bc) {  // diagonal block: mirror the lower triangle
+        const int64_t gi = I0 + a, gj = I0 + bc;
+        const double v = (gi < n && gj < n) ? A[gi + gj * lda] : 0.0;
+        at[bc * P + a] = v;
+        at[a * P + bc] = v;
+      }
+    }
+    for (int e = tid; e < 64 * NR; e += 256) {
+      const int jj = e % 64, cc = e / 64;
+      const int64_t gj = J0 + jj;
+      xs[jj * NR + cc] = (gj < n && cc < nc) ? X[gj + (c0 + cc) * ldx] : 0.0;
+    }
+    __syncthreads();
+    for (int jj = h * 16; jj < h * 16 + 16; ++jj) {
+      const double av = at[jj * P + o];
+#pragma unroll
+      for (int cc = 0; cc < NR; ++cc) {
+        const double xv = xs[jj * NR + cc];
+        const double p = av * xv;
+        const double pe = fma(av, xv, -p);
+        double s1, e1;
+        two_sum(hs[cc], p, s1, e1);
+        hs[cc] = s1;
+        he[cc] += e1 + pe;
+      }
+    }
+  }
+#pragma unroll
+  for (int cc = 0; cc < NR; ++cc) {
+    red_s[(h * 64 + o) * NR + cc] = hs[cc];
+    red_e[(h * 64 + o) * NR + cc] = he[cc];
+  }
+  __syncthreads();
+  if (h == 0) {
+    const int64_t row = I0 + o;
+    if (row < n) {
+      for (int cc = 0; cc < nc; ++cc) {
+        double s = red_s[o * NR + cc], e = red_e[o * NR + cc];
+        for (int q = 1; q < 4; ++q) {
+          double s1, e1;
+          two_sum(s, red_s[(q * 64 + o) * NR + cc], s1, e1);
+          s = s1;
+          e += e1 + red_e[(q * 64 + o) * NR + cc];
+        }
+        double r1, r2;
+        two_sum(Bm ? Bm[row + (c0 + cc) * ldb] : 0.0, -s, r1, r2);
+        R[row + (c0 + cc) * ldr] = r1 + (r2 - e);
+      }
+    }
+  }
+}
+
+// Column dot products, two passes.  Pass 1: grid (nblk, nrhs), each block
+// reduces a fixed strided set of rows.  Pass 2: one block per column sums
+// the nblk partials in index order.
+constexpr int kDotBlocks = 128;
+
+__global__ __launch_bounds__(256) void col_dot_partial(const double *__restrict__ x, int64_t ldx,
+                                                       const double *__restrict__ y, int64_t ldy,
+                                                       int64_t n, double *__restrict__ partial) {
+  __shared__ double sm[256];
+  const int64_t c = blockIdx.y;
+  const int tid = threadIdx.x;
+  double s = 0.0;
+  for (int64_t r = (int64_t)blockIdx.x * 256 + tid; r < n; r += (int64_t)kDotBlocks * 256)
+    s += x[r + c * ldx] * y[r + c * ldy];
+  sm[tid] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (tid < w) sm[tid] += sm[tid + w];
+    __syncthreads();
+  }
+  if (tid == 0) partial[c * kDotBlocks + blockIdx.x] = sm[0];
+}
+
+__global__ __launch_bounds__(128) void col_dot_final(const double *__restrict__ partial,
+                                                     double *__restrict__ out) {
+  __shared__ double sm[kDotBlocks];
+  const int64_t c = blockIdx.x;
+  const int tid = threadIdx.x;
+  sm[tid] = partial[c * kDotBlocks + tid];
+  __syncthreads();
+  for (int w = kDotBlocks / 2; w > 0; w >>= 1) {
+    if (tid < w) sm[tid] += sm[tid + w];
+    __syncthreads();
+  }
+  if (tid == 0) out[c] = sm[0];
+}
+
+// y = sgn * a[c] * x + bcoef[c] * y on active columns.
+__global__ void axpby_kernel(const double *__restrict__ x, int64_t ldx, double *__restrict__ y,
+                             int64_t ldy, int64_t n, int64_t nrhs, const double *__restrict__ a,
+                             double sgn, const double *__restrict__ bcoef,
+                             const int32_t *__restrict__ active) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n * nrhs) return;
+  const int64_t r = e % n, c = e / n;
+  if (active && !active[c]) return;
+  const double av = sgn * (a ? a[c] : 1.0);
+  const double bv = bcoef ? bcoef[c] : 1.0;
+  y[r + c * ldy] = av * x[r + c * ldx] + bv * y[r + c * ldy];
+}
+
+__global__ void copy_kernel(const double *__restrict__ x, int64_t ldx, double *__restrict__ y,
+                            int64_t ldy, int64_t n, int64_t nrhs) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n * nrhs) return;
+  const int64_t r = e % n, c = e / n;
+  y[r + c * ldy] = x[r + c * ldx];
+}
+
+}  // namespace
+
+void launch_symm_residual(const double *A, int64_t lda, int64_t n, const double *X, int64_t ldx,
+                          const double *B, int64_t ldb, double *R, int64_t ldr, int64_t nrhs,
+                          hipStream_t s) {
+  if (n <= 0 || nrhs <= 0) return;
+  const unsigned gx = (unsigned)((n + 63) / 64);
+  if (nrhs == 1)
+    hipLaunchKernelGGL(symm_residual_kernel<1>, dim3(gx, 1), dim3(256), 0, s, A, lda, n, X, ldx,
+                       B, ldb, R, ldr, nrhs);
+  else
+    hipLaunchKernelGGL(symm_residual_kernel<8>, dim3(gx, (unsigned)((nrhs + 7) / 8)), dim3(256),
+                       0, s, A, lda, n, X, ldx, B, ldb, R, ldr, nrhs);
+}
+
+void launch_col_dot(const double *x, int64_t ldx, const double *y, int64_t ldy, int64_t n,
+                    int64_t nrhs, double *out, double *partial, hipStream_t s) {
+  if (nrhs <= 0) return;
+  hipLaunchKernelGGL(col_dot_partial, dim3(kDotBlocks, (unsigned)nrhs), dim3(256), 0, s, x, ldx,
+                     y, ldy, n, partial);
+  hipLaunchKernelGGL(col_dot_final, dim3((unsigned)nrhs), dim3(kDotBlocks), 0, s, partial, out);
+}
+
+void launch_axpby(const double *x, int64_t ldx, double *y, int64_t ldy, int64_t n, int64_t nrhs,
+                  const double *a, double a_sign, const double *bcoef, const int32_t *active,
+                  hipStream_t s) {
+  const int64_t tot = n * nrhs;
+  if (tot <= 0) return;
+  hipLaunchKernelGGL(axpby_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, x, ldx,
+                     y, ldy, n, nrhs, a, a_sign, bcoef, active);
+}
+
+void launch_copy(const double *x, int64_t ldx, double *y, int64_t ldy, int64_t n, int64_t nrhs,
+                 hipStream_t s) {
+  const int64_t tot = n * nrhs;
+  if (tot <= 0) return;
+  hipLaunchKernelGGL(copy_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, x, ldx, y,
+                     ldy, n, nrhs);
+}
+
+}  // namespace chol

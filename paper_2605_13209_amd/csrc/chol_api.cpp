@@ -1,0 +1,627 @@
+// Host runtime and C ABI of the MI355X dense SPD / GP solver.
+//
+// The factorisation driver is the blocked right-looking algorithm of the
+// paper (first algorithm figure, right column): for each column of tiles,
+// Step 1 factors the diagonal tile, Step 2 solves the tiles below it, and
+// Step 3 updates every trailing tile.  Two gfx950-specific changes of
+// schedule, neither of which changes what is computed:
+//  * panel width w: the Step-3 update of w consecutive tile columns is
+//    applied to the far trailing matrix in one pass (inner dimension w*b),
+//    which divides the trailing matrix's HBM traffic by w; the w columns
+//    themselves are updated column by column before they are factored.
+//  * lookahead: the update of the next w columns is split off and run,
+//    together with their Steps 1-2, on a second stream, concurrently with
+//    the bulk of the current trailing update.
+// Every tile receives the same sequence of updates in the same order with or
+// without these options, so results are bitwise identical across them.
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <vector>
+
+#include "../../include/chol.h"
+#include "internal.hpp"
+
+using namespace chol;
+
+namespace {
+
+constexpr size_t kHeader = 256;  // info word + reserved, at the start of the workspace
+
+struct Options {
+  std::atomic<int64_t> panel_width{2};
+  std::atomic<int64_t> lookahead{1};
+  std::atomic<int64_t> super_tile{8};
+  std::atomic<int64_t> graph{0};
+  std::atomic<int64_t> profile{0};
+};
+Options g_opt;
+
+// Per-device side stream and events (created on first use, never destroyed).
+struct DeviceCtx {
+  bool ready = false;
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_panel = nullptr, ev_bulk = nullptr, ev_join = nullptr;
+};
+std::mutex g_ctx_mu;
+DeviceCtx g_ctx[64];
+
+int get_ctx(DeviceCtx **out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return CHOL_ERR_HIP;
+  std::lock_guard<std::mutex> lk(g_ctx_mu);
+  DeviceCtx &c = g_ctx[dev];
+  if (!c.ready) {
+    if (hipStreamCreateWithFlags(&c.side, hipStreamNonBlocking) != hipSuccess) return CHOL_ERR_HIP;
+    const unsigned fl = hipEventDisableTiming;
+    if (hipEventCreateWithFlags(&c.ev_fork, fl) != hipSuccess ||
+        hipEventCreateWithFlags(&c.ev_panel, fl) != hipSuccess ||
+        hipEventCreateWithFlags(&c.ev_bulk, fl) != hipSuccess ||
+        hipEventCreateWithFlags(&c.ev_join, fl) != hipSuccess)
+      return CHOL_ERR_HIP;
+    c.ready = true;
+  }
+  *out = &c;
+  return CHOL_OK;
+}
+
+// Event-bracketed timing of the trailing-update launches (option "profile").
+struct ProfRec {
+  hipEvent_t a, b;
+  double flops;
+};
+std::mutex g_prof_mu;
+std::vector<ProfRec> g_prof;      // recorded, not yet read
+std::vector<hipEvent_t> g_ev_free;
+double g_prof_ms = 0.0, g_prof_flops = 0.0;
+int64_t g_prof_n = 0;
+
+hipEvent_t prof_event() {
+  if (!g_ev_free.empty()) {
+    hipEvent_t e = g_ev_free.back();
+    g_ev_free.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Algorithmic flops of one update launch (see chol.h, kernel timing).
+double update_flops(int b, int64_t N, int pw, int64_t k0, int64_t k1, int mode) {
+  const double K = (double)pw * b, bb = (double)b;
+  const int64_t R = N - k0;
+  int64_t ndiag, noff;
+  if (mode == 0) {
+    ndiag = R;
+    noff = R * (R - 1) / 2;
+  } else {
+    const int64_t Kc = k1 - k0;
+    ndiag = Kc;
+    noff = Kc * (Kc - 1) / 2 + (R - Kc) * Kc;
+  }
+  return (double)noff * 2.0 * bb * bb * K + (double)ndiag * bb * (bb + 1.0) * K;
+}
+
+// launch_update, bracketed by events when profiling.
+void update(void *tiles, int st, int b, int64_t N, int64_t p0, int pw, int64_t k0, int64_t k1,
+            int mode, int S, int fp16, const int64_t *info, hipStream_t s) {
+  if (N - k0 <= 0 || (mode == 1 && k1 <= k0)) return;
+  if (!g_opt.profile) {
+    launch_update(tiles, st, b, N, p0, pw, k0, k1, mode, S, fp16, info, s);
+    return;
+  }
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  hipEvent_t a = prof_event(), e = prof_event();
+  if (a) (void)hipEventRecord(a, s);
+  launch_update(tiles, st, b, N, p0, pw, k0, k1, mode, S, fp16, info, s);
+  if (e) (void)hipEventRecord(e, s);
+  if (a && e) g_prof.push_back({a, e, update_flops(b, N, pw, k0, k1, mode)});
+}
+
+int store_of(int precision) { return precision == CHOL_FP64 ? STORE_F64 : STORE_F32; }
+size_t esize_of(int precision) { return precision == CHOL_FP64 ? 8 : 4; }
+bool tile_ok(int tile) { return tile == 64 || tile == 128; }
+
+}  // namespace
+
+struct chol_factor_s {
+  int64_t n = 0, N = 0;
+  int b = 0, precision = 0, device = 0;
+  void *tiles = nullptr;
+  int64_t *d_info = nullptr;
+  double scale = 1.0;  // CHOL_FP16_SCALED: the factor of A / scale is stored
+  hipStream_t stream = nullptr;
+  int64_t info = -1;  // host copy once known
+};
+
+#define HIP_OK(x)                              \
+  do {                                         \
+    if ((x) != hipSuccess) return CHOL_ERR_HIP; \
+  } while (0)
+
+extern "C" {
+
+const char *chol_status_string(int status) {
+  switch (status) {
+    case CHOL_OK: return "success";
+    case CHOL_ERR_HIP: return "HIP runtime error";
+    case CHOL_ERR_WORKSPACE: return "workspace too small";
+    case CHOL_ERR_NOT_CONVERGED: return "refinement did not converge";
+    case CHOL_ERR_NOT_SPD: return "matrix is not positive definite";
+    case CHOL_ERR_UNSUPPORTED: return "unsupported precision or tile";
+    case CHOL_ERR_BAD_HANDLE: return "invalid factor handle";
+    default: break;
+  }
+  if (status < 0 && status > -64) return "invalid argument";
+  return "unknown status";
+}
+
+int chol_set_option(const char *key, int64_t value) {
+  if (!key) return -1;
+  if (!strcmp(key, "panel_width")) {
+    if (value < 1 || value > 8) return -2;
+    g_opt.panel_width = value;
+  } else if (!strcmp(key, "lookahead")) {
+    if (value < 0 || value > 1) return -2;
+    g_opt.lookahead = value;
+  } else if (!strcmp(key, "super_tile")) {
+    if (value < 1 || value > 64) return -2;
+    g_opt.super_tile = value;
+  } else if (!strcmp(key, "graph")) {
+    if (value < 0 || value > 1) return -2;
+    g_opt.graph = value;
+  } else if (!strcmp(key, "profile")) {
+    if (value < 0 || value > 1) return -2;
+    g_opt.profile = value;
+  } else {
+    return -1;
+  }
+  return CHOL_OK;
+}
+
+int64_t chol_get_option(const char *key) {
+  if (!key) return -1;
+  if (!strcmp(key, "panel_width")) return g_opt.panel_width;
+  if (!strcmp(key, "lookahead")) return g_opt.lookahead;
+  if (!strcmp(key, "super_tile")) return g_opt.super_tile;
+  if (!strcmp(key, "graph")) return g_opt.graph;
+  if (!strcmp(key, "profile")) return g_opt.profile;
+  return -1;
+}
+
+int chol_profile_read(double *ms, int64_t *launches, double *flops) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  for (const ProfRec &r : g_prof) {
+    float t = 0.0f;
+    if (hipEventSynchronize(r.b) != hipSuccess || hipEventElapsedTime(&t, r.a, r.b) != hipSuccess)
+      return CHOL_ERR_HIP;
+    g_prof_ms += t;
+    g_prof_flops += r.flops;
+    ++g_prof_n;
+    g_ev_free.push_back(r.a);
+    g_ev_free.push_back(r.b);
+  }
+  g_prof.clear();
+  if (ms) *ms = g_prof_ms;
+  if (launches) *launches = g_prof_n;
+  if (flops) *flops = g_prof_flops;
+  return CHOL_OK;
+}
+
+void chol_profile_reset(void) {
+  double ms;
+  int64_t l;
+  double f;
+  (void)chol_profile_read(&ms, &l, &f);
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  g_prof_ms = g_prof_flops = 0.0;
+  g_prof_n = 0;
+}
+
+int chol_tile_default(int64_t n, int precision) {
+  (void)precision;
+  return n <= 512 ? 64 : 128;
+}
+
+size_t chol_factor_bytes(int64_t n, int precision, int tile) {
+  if (n < 0 || precision < CHOL_FP64 || precision > CHOL_FP16_SCALED) return 0;
+  if (tile == 0) tile = chol_tile_default(n, precision);
+  if (!tile_ok(tile)) return 0;
+  const int64_t N = (n + tile - 1) / tile;
+  return kHeader + (size_t)tile_count(N) * (size_t)tile * (size_t)tile * esize_of(precision);
+}
+
+int gp_assemble(const double *X, int64_t n, int64_t d, int64_t ldx, double lengthscale,
+                double variance, double noise, double *A, int64_t lda, int uplo_full,
+                void *stream) {
+  if (n > 0 && !X) return -1;
+  if (n < 0) return -2;
+  if (d < 1) return -3;
+  if (ldx < d) return -4;
+  if (!(lengthscale > 0.0)) return -5;
+  if (!(variance >= 0.0)) return -6;
+  if (!(noise >= 0.0)) return -7;
+  if (n > 0 && !A) return -8;
+  if (lda < (n > 1 ? n : 1)) return -9;
+  const double two_l2 = 2.0 * lengthscale * lengthscale;
+  launch_gp_assemble(X, n, d, ldx, two_l2, variance, noise, A, lda, uplo_full ? 1 : 0,
+                     (hipStream_t)stream);
+  return hipGetLastError() == hipSuccess ? CHOL_OK : CHOL_ERR_HIP;
+}
+
+// Steps 1-2 (and the in-panel Step 3) of panel columns [c0, c1).
+static void factor_panel(chol_factor_s *F, int64_t c0, int64_t c1, int st, hipStream_t s) {
+  const int64_t N = F->N;
+  const int b = F->b;
+  const int fp16 = F->precision == CHOL_FP16_SCALED;
+  for (int64_t c = c0; c < c1; ++c) {
+    launch_potrf(F->tiles, st, b, N, c, F->d_info, s);
+    launch_trsm(F->tiles, st, b, N, c, F->d_info, s);
+    if (c + 1 < c1)
+      update(F->tiles, st, b, N, c, 1, c + 1, c1, /*band*/ 1, 8, fp16, F->d_info, s);
+  }
+}
+
+int chol_factor(const double *A, int64_t n, int64_t lda, int precision, int tile,
+                void *workspace, size_t ws_bytes, chol_handle *Fout, int64_t *info,
+                void *stream) {
+  if (n > 0 && !A) return -1;
+  if (n < 0) return -2;
+  if (lda < (n > 1 ? n : 1)) return -3;
+  if (precision < CHOL_FP64 || precision > CHOL_FP16_SCALED) return -4;
+  if (tile == 0) tile = chol_tile_default(n, precision);
+  if (!tile_ok(tile)) return -5;
+  if (!workspace || ((uintptr_t)workspace & 255)) return -6;
+  const size_t need = chol_factor_bytes(n, precision, tile);
+  if (ws_bytes < need) return CHOL_ERR_WORKSPACE;
+  if (!Fout) return -8;
+  if (precision == CHOL_FP16_SCALED && tile != 128) return CHOL_ERR_UNSUPPORTED;
+
+  DeviceCtx *ctx = nullptr;
+  int rc = get_ctx(&ctx);
+  if (rc) return rc;
+
+  chol_factor_s *F = new chol_factor_s();
+  F->n = n;
+  F->b = tile;
+  F->N = (n + tile - 1) / tile;
+  F->precision = precision;
+  (void)hipGetDevice(&F->device);
+  F->d_info = (int64_t *)workspace;
+  F->tiles = (char *)workspace + kHeader;
+  F->stream = (hipStream_t)stream;
+  const int st = store_of(precision);
+  const int64_t N = F->N;
+  const int b = F->b;
+  hipStream_t s = F->stream;
+
+  // Scaling for the FP16 form: the factor of H = A / s is computed, with s
+  // the largest diagonal entry (one read-back of the diagonal).
+  double pack_scale = 1.0;
+  if (precision == CHOL_FP16_SCALED && n > 0) {
+    std::vector<double> diag((size_t)n);
+    HIP_OK(hipStreamSynchronize(s));
+    HIP_OK(hipMemcpy2D(diag.data(), sizeof(double), A, (size_t)(lda + 1) * sizeof(double),
+                       sizeof(double), (size_t)n, hipMemcpyDeviceToHost));
+    double mx = 0.0;
+    for (double v : diag) mx = std::fmax(mx, v);
+    if (!(mx > 0.0)) mx = 1.0;
+    F->scale = mx;
+    pack_scale = 1.0 / mx;
+  }
+
+  launch_clear_i64(F->d_info, 1, s);
+  launch_pack(A, n, lda, F->tiles, st, b, N, pack_scale, s);
+
+  const int64_t w = g_opt.panel_width;
+  const int S = (int)g_opt.super_tile;
+  const int fp16 = precision == CHOL_FP16_SCALED;
+  const bool la = g_opt.lookahead != 0 && N > w;
+
+  if (!la) {
+    for (int64_t c0 = 0; c0 < N; c0 += w) {
+      const int64_t c1 = std::min<int64_t>(c0 + w, N);
+      factor_panel(F, c0, c1, st, s);
+      if (c1 < N)
+        update(F->tiles, st, b, N, c0, (int)(c1 - c0), c1, N, /*tri*/ 0, S, fp16, F->d_info, s);
+    }
+  } else {
+    hipStream_t p = ctx->side;
+    HIP_OK(hipEventRecord(ctx->ev_fork, s));
+    HIP_OK(hipStreamWaitEvent(p, ctx->ev_fork, 0));
+    factor_panel(F, 0, std::min<int64_t>(w, N), st, p);
+    for (int64_t c0 = 0; c0 < N; c0 += w) {
+      const int64_t c1 = std::min<int64_t>(c0 + w, N);  // current panel [c0, c1)
+      const int64_t n1 = std::min<int64_t>(c1 + w, N);  // next panel [c1, n1)
+      HIP_OK(hipEventRecord(ctx->ev_panel, p));          // panel [c0, c1) finished
+      if (c1 < N) {
+        // next panel: its update by this panel (after the previous bulk update,
+        // which also wrote it), then its Steps 1-2, all on the side stream.
+        if (c0 > 0) HIP_OK(hipStreamWaitEvent(p, ctx->ev_bulk, 0));
+        update(F->tiles, st, b, N, c0, (int)(c1 - c0), c1, n1, /*band*/ 1, 8, fp16, F->d_info, p);
+        factor_panel(F, c1, n1, st, p);
+      }
+      // bulk update of the columns right of the next panel, on the main stream
+      HIP_OK(hipStreamWaitEvent(s, ctx->ev_panel, 0));
+      if (n1 < N) {
+        update(F->tiles, st, b, N, c0, (int)(c1 - c0), n1, N, /*tri*/ 0, S, fp16, F->d_info, s);
+      }
+      HIP_OK(hipEventRecord(ctx->ev_bulk, s));
+    }
+    HIP_OK(hipEventRecord(ctx->ev_join, p));
+    HIP_OK(hipStreamWaitEvent(s, ctx->ev_join, 0));
+  }
+  if (hipGetLastError() != hipSuccess) {
+    delete F;
+    return CHOL_ERR_HIP;
+  }
+  *Fout = F;
+  if (info) {
+    rc = chol_get_info(F, info);
+    if (rc) return rc;
+  }
+  return CHOL_OK;
+}
+
+int chol_get_info(chol_handle F, int64_t *info) {
+  if (!F) return CHOL_ERR_BAD_HANDLE;
+  if (F->info < 0) {
+    int64_t v = 0;
+    HIP_OK(hipStreamSynchronize(F->stream));
+    HIP_OK(hipMemcpy(&v, F->d_info, sizeof(int64_t), hipMemcpyDeviceToHost));
+    F->info = v;
+  }
+  if (info) *info = F->info;
+  return CHOL_OK;
+}
+
+int64_t chol_factor_n(chol_handle F) { return F ? F->n : -1; }
+int chol_factor_tile(chol_handle F) { return F ? F->b : -1; }
+int chol_factor_precision(chol_handle F) { return F ? F->precision : -1; }
+
+void chol_factor_free(chol_handle F) { delete F; }
+
+int chol_solve(chol_handle F, double *B, int64_t nrhs, int64_t ldb, void *stream) {
+  if (!F) return CHOL_ERR_BAD_HANDLE;
+  if (nrhs > 0 && !B) return -2;
+  if (nrhs < 0) return -3;
+  if (ldb < (F->n > 1 ? F->n : 1)) return -4;
+  if (F->info > 0) return CHOL_ERR_NOT_SPD;
+  hipStream_t s = (hipStream_t)stream;
+  const int st = store_of(F->precision);
+  launch_trsv_fwd(F->tiles, st, F->b, F->N, F->n, B, ldb, nrhs, s);
+  launch_trsv_bwd(F->tiles, st, F->b, F->N, F->n, B, ldb, nrhs, s);
+  if (F->scale != 1.0) launch_scale(B, F->n, ldb, nrhs, 1.0 / F->scale, s);
+  return hipGetLastError() == hipSuccess ? CHOL_OK : CHOL_ERR_HIP;
+}
+
+int chol_factor_to_dense(chol_handle F, double *L, int64_t ldl, void *stream) {
+  if (!F) return CHOL_ERR_BAD_HANDLE;
+  if (F->n > 0 && !L) return -2;
+  if (ldl < (F->n > 1 ? F->n : 1)) return -3;
+  launch_unpack(F->tiles, store_of(F->precision), F->b, F->N, F->n, std::sqrt(F->scale), L, ldl,
+                (hipStream_t)stream);
+  return hipGetLastError() == hipSuccess ? CHOL_OK : CHOL_ERR_HIP;
+}
+
+int chol_residual(const double *A, int64_t lda, int64_t n, const double *X, int64_t ldx,
+                  const double *B, int64_t ldb, double *R, int64_t ldr, int64_t nrhs,
+                  void *stream) {
+  if (n > 0 && !A) return -1;
+  if (lda < (n > 1 ? n : 1)) return -2;
+  if (n < 0) return -3;
+  if (nrhs < 0) return -10;
+  if (n > 0 && nrhs > 0 && (!X || !B || !R)) return -4;
+  if (ldx < (n > 1 ? n : 1)) return -5;
+  if (ldb < (n > 1 ? n : 1)) return -7;
+  if (ldr < (n > 1 ? n : 1)) return -9;
+  launch_symm_residual(A, lda, n, X, ldx, B, ldb, R, ldr, nrhs, (hipStream_t)stream);
+  return hipGetLastError() == hipSuccess ? CHOL_OK : CHOL_ERR_HIP;
+}
+
+// ---------------------------------------------------------- refinement ----
+// Workspace layout (FP64, each n x nrhs block with leading dimension n):
+//   r, d [IR];  r, z, p, q [PCG];  then scalars: 8 arrays of nrhs doubles and
+//   the dot-product partials (128 * nrhs doubles).
+size_t chol_refine_bytes(int64_t n, int64_t nrhs, int method) {
+  if (n < 0 || nrhs < 0) return 0;
+  const int64_t blocks = method == CHOL_REFINE_PCG ? 4 : 2;
+  const size_t vec = (size_t)n * (size_t)nrhs * sizeof(double);
+  return blocks * vec + (size_t)(8 + 128) * (size_t)nrhs * sizeof(double) + 256;
+}
+
+int chol_refine_solve(chol_handle F, const double *A, int64_t lda, const double *Xf, int64_t d,
+                      int64_t ldxf, double lengthscale, double variance, double noise,
+                      const double *B, int64_t ldb, double *X, int64_t ldxs, int64_t nrhs,
+                      double tol, int max_iter, int method, void *workspace, size_t ws_bytes,
+                      chol_refine_report *rep, void *stream) {
+  const auto t0 = std::chrono::steady_clock::now();
+  if (!F) return CHOL_ERR_BAD_HANDLE;
+  const int64_t n = F->n;
+  if (A && lda < (n > 1 ? n : 1)) return -3;
+  if (!A && (!Xf || d < 1 || ldxf < d || !(lengthscale > 0.0))) return -4;
+  if (nrhs > 0 && (!B || !X)) return -10;
+  if (ldb < (n > 1 ? n : 1)) return -11;
+  if (ldxs < (n > 1 ? n : 1)) return -13;
+  if (nrhs < 0) return -14;
+  if (!(tol > 0.0)) return -15;
+  if (max_iter < 0) return -16;
+  if (method != CHOL_REFINE_IR && method != CHOL_REFINE_PCG) return -17;
+  if (ws_bytes < chol_refine_bytes(n, nrhs, method) || (!workspace && nrhs > 0))
+    return CHOL_ERR_WORKSPACE;
+  if (F->info < 0) {
+    int64_t inf;
+    int rc = chol_get_info(F, &inf);
+    if (rc) return rc;
+  }
+  if (F->info > 0) return CHOL_ERR_NOT_SPD;
+  if (rep) memset(rep, 0, sizeof(*rep));
+  if (n == 0 || nrhs == 0) {
+    if (rep) rep->converged = 1;
+    return CHOL_OK;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  const size_t vec = (size_t)n * (size_t)nrhs;
+  double *r = (double *)workspace;
+  double *dv = r + vec;  // IR correction / PCG z
+  double *pv = dv + vec;  // PCG only
+  double *qv = pv + vec;  // PCG only
+  double *scal = (double *)workspace + (method == CHOL_REFINE_PCG ? 4 : 2) * vec;
+  double *rr = scal, *xx = scal + nrhs, *rho = scal + 2 * nrhs, *rho_new = scal + 3 * nrhs,
+         *pq = scal + 4 * nrhs, *alpha = scal + 5 * nrhs, *beta = scal + 6 * nrhs;
+  double *partial = scal + 8 * nrhs;
+  const double lam = noise;
+  const bool certify = lam > 0.0;
+
+  auto residual = [&](const double *x, double *out) {
+    if (A)
+      launch_symm_residual(A, lda, n, x, ldxs, B, ldb, out, n, nrhs, s);
+    else
+      launch_gp_residual(Xf, n, d, ldxf, 2.0 * lengthscale * lengthscale, variance, noise, x,
+                         ldxs, B, ldb, out, n, nrhs, s);
+  };
+  auto msolve = [&](double *v) { chol_solve(F, v, nrhs, n, s); };
+  std::vector<double> h_rr(nrhs), h_xx(nrhs), h_a(nrhs), h_b(nrhs);
+  auto fetch_norms = [&](const double *v, const double *x) -> int {
+    launch_col_dot(v, n, v, n, n, nrhs, rr, partial, s);
+    launch_col_dot(x, ldxs, x, ldxs, n, nrhs, xx, partial + 64 * 0, s);
+    if (hipMemcpyAsync(h_rr.data(), rr, nrhs * sizeof(double), hipMemcpyDeviceToHost, s) !=
+            hipSuccess ||
+        hipMemcpyAsync(h_xx.data(), xx, nrhs * sizeof(double), hipMemcpyDeviceToHost, s) !=
+            hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      return CHOL_ERR_HIP;
+    return CHOL_OK;
+  };
+
+  // x0 = F^-T F^-1 b
+  launch_copy(B, ldb, X, ldxs, n, nrhs, s);
+  msolve(X);
+  int iters = 0;
+  bool conv = false;
+  double cert_max = INFINITY, res_max = INFINITY;
+  auto certify_now = [&](const double *res) -> int {
+    int rc = fetch_norms(res, X);
+    if (rc) return rc;
+    cert_max = 0.0;
+    res_max = 0.0;
+    for (int64_t c = 0; c < nrhs; ++c) {
+      const double rn = std::sqrt(h_rr[c]), xn = std::sqrt(h_xx[c]);
+      res_max = std::fmax(res_max, rn);
+      const double ce = certify ? rn / (lam * xn) : INFINITY;
+      cert_max = std::fmax(cert_max, std::isnan(ce) ? INFINITY : ce);
+    }
+    return CHOL_OK;
+  };
+
+  if (method == CHOL_REFINE_IR) {
+    for (;;) {
+      residual(X, r);
+      int rc = certify_now(r);
+      if (rc) return rc;
+      if (certify && cert_max <= 0.5 * tol) {
+        conv = true;
+        break;
+      }
+      if (iters >= max_iter) break;
+      launch_copy(r, n, dv, n, n, nrhs, s);
+      msolve(dv);
+      launch_axpby(dv, n, X, ldxs, n, nrhs, nullptr, 1.0, nullptr, nullptr, s);
+      ++iters;
+      if (!certify) {
+        // ||d|| <= tol ||x||
+        rc = fetch_norms(dv, X);
+        if (rc) return rc;
+        bool all = true;
+        for (int64_t c = 0; c < nrhs; ++c)
+          all = all && std::sqrt(h_rr[c]) <= tol * std::sqrt(h_xx[c]);
+        cert_max = 0.0;
+        for (int64_t c = 0; c < nrhs; ++c)
+          cert_max = std::fmax(cert_max, std::sqrt(h_rr[c]) / std::sqrt(h_xx[c]));
+        if (all) {
+          conv = true;
+          break;
+        }
+      }
+    }
+  } else {
+    // PCG with M = F F^T, starting from x0 = M^-1 b.
+    double *z = dv;
+    residual(X, r);
+    int rc = certify_now(r);
+    if (rc) return rc;
+    if (certify && cert_max <= 0.5 * tol) conv = true;
+    if (!conv) {
+      launch_copy(r, n, z, n, n, nrhs, s);
+      msolve(z);
+      launch_copy(z, n, pv, n, n, nrhs, s);
+      launch_col_dot(r, n, z, n, n, nrhs, rho, partial, s);
+      std::vector<double> h_rho(nrhs), h_pq(nrhs);
+      HIP_OK(hipMemcpyAsync(h_rho.data(), rho, nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
+      HIP_OK(hipStreamSynchronize(s));
+      while (iters < max_iter) {
+        // q = -(A p): the residual kernels with no right-hand side
+        if (A)
+          launch_symm_residual(A, lda, n, pv, n, nullptr, n, qv, n, nrhs, s);
+        else
+          launch_gp_residual(Xf, n, d, ldxf, 2.0 * lengthscale * lengthscale, variance, noise, pv,
+                             n, nullptr, n, qv, n, nrhs, s);
+        launch_col_dot(pv, n, qv, n, n, nrhs, pq, partial, s);
+        HIP_OK(hipMemcpyAsync(h_pq.data(), pq, nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIP_OK(hipStreamSynchronize(s));
+        for (int64_t c = 0; c < nrhs; ++c) {
+          const double den = -h_pq[c];
+          h_a[c] = (den != 0.0 && std::isfinite(den)) ? h_rho[c] / den : 0.0;
+        }
+        HIP_OK(hipMemcpyAsync(alpha, h_a.data(), nrhs * sizeof(double), hipMemcpyHostToDevice, s));
+        launch_axpby(pv, n, X, ldxs, n, nrhs, alpha, 1.0, nullptr, nullptr, s);  // x += a p
+        launch_axpby(qv, n, r, n, n, nrhs, alpha, 1.0, nullptr, nullptr, s);     // r += a q = r - a A p
+        ++iters;
+        rc = certify_now(r);
+        if (rc) return rc;
+        if (certify && cert_max <= 0.5 * tol) {
+          // confirm on the true residual
+          residual(X, r);
+          rc = certify_now(r);
+          if (rc) return rc;
+          if (cert_max <= 0.5 * tol) {
+            conv = true;
+            break;
+          }
+        }
+        if (iters % 50 == 0) residual(X, r);
+        launch_copy(r, n, z, n, n, nrhs, s);
+        msolve(z);
+        launch_col_dot(r, n, z, n, n, nrhs, rho_new, partial, s);
+        std::vector<double> h_rn(nrhs);
+        HIP_OK(hipMemcpyAsync(h_rn.data(), rho_new, nrhs * sizeof(double), hipMemcpyDeviceToHost,
+                              s));
+        HIP_OK(hipStreamSynchronize(s));
+        for (int64_t c = 0; c < nrhs; ++c) {
+          h_b[c] = (h_rho[c] != 0.0) ? h_rn[c] / h_rho[c] : 0.0;
+          h_rho[c] = h_rn[c];
+        }
+        HIP_OK(hipMemcpyAsync(beta, h_b.data(), nrhs * sizeof(double), hipMemcpyHostToDevice, s));
+        launch_axpby(z, n, pv, n, n, nrhs, nullptr, 1.0, beta, nullptr, s);  // p = z + beta p
+      }
+    }
+  }
+  HIP_OK(hipStreamSynchronize(s));
+  if (rep) {
+    rep->iters = iters;
+    rep->converged = conv ? 1 : 0;
+    rep->cert = cert_max;
+    rep->resid_norm = res_max;
+    rep->time_ms =
+        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  }
+  return conv ? CHOL_OK : CHOL_ERR_NOT_CONVERGED;
+}
+
+}  // extern "C"

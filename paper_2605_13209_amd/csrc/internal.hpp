@@ -1,0 +1,89 @@
+// Internal declarations shared by the HIP kernels and the host scheduler.
+//
+// Factor storage (the paper's layout, Implementation section: only the
+// lower-triangular and diagonal square blocks are stored): an order-n matrix
+// is padded to N = ceil(n / b) tiles of side b; tile (i, c), i >= c, is one
+// contiguous column-major b x b block.  Tiles are ordered column of tiles by
+// column of tiles, so the panel below a diagonal block (Step 2 of the blocked
+// algorithm) is one contiguous range.  Padding rows/columns hold the identity,
+// so the factor of the padded matrix is diag(L, I) exactly.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace chol {
+
+__host__ __device__ inline int64_t tile_col_offset(int64_t c, int64_t N) {
+  return c * N - (c * (c - 1)) / 2;
+}
+__host__ __device__ inline int64_t tile_index(int64_t i, int64_t c, int64_t N) {
+  return tile_col_offset(c, N) + (i - c);
+}
+__host__ __device__ inline int64_t tile_count(int64_t N) { return N * (N + 1) / 2; }
+
+// Element storage kinds of the factor.
+enum Store : int { STORE_F64 = 0, STORE_F32 = 1 };
+
+// ---- launchers (all asynchronous on `s`) --------------------------------
+// gp_assemble into a column-major matrix.
+void launch_gp_assemble(const double *X, int64_t n, int64_t d, int64_t ldx, double inv2l2,
+                        double var, double noise, double *A, int64_t lda, int full,
+                        hipStream_t s);
+// Matrix-free GP residual R = B - (K + noise I) Xs.
+void launch_gp_residual(const double *F, int64_t n, int64_t d, int64_t ldf, double inv2l2,
+                        double var, double noise, const double *Xs, int64_t ldxs,
+                        const double *B, int64_t ldb, double *R, int64_t ldr, int64_t nrhs,
+                        hipStream_t s);
+
+// Clear the info word (a kernel, not a memset, so graph capture is safe).
+void launch_clear_i64(int64_t *p, int count, hipStream_t s);
+
+// Column-major FP64 A (lower) -> packed tiles, scaled by `scale`, identity padding.
+void launch_pack(const double *A, int64_t n, int64_t lda, void *tiles, int store, int b,
+                 int64_t N, double scale, hipStream_t s);
+// Packed tiles -> dense column-major FP64 L (upper set to zero), times `scale`.
+void launch_unpack(const void *tiles, int store, int b, int64_t N, int64_t n, double scale,
+                   double *L, int64_t ldl, hipStream_t s);
+
+// Step 1: factor diagonal tile c in place (FP64 arithmetic).  Sets *info.
+void launch_potrf(void *tiles, int store, int b, int64_t N, int64_t c, int64_t *info,
+                  hipStream_t s);
+// Step 2: tiles (i, c), i in [c+1, N): X <- X L_cc^{-T} (FP64 arithmetic).
+void launch_trsm(void *tiles, int store, int b, int64_t N, int64_t c, const int64_t *info,
+                 hipStream_t s);
+// Step 3: C_ik -= sum_{p in [p0, p0+pw)} L_ip L_kp^T over the region
+//   mode 0 (triangle): k0 <= k <= i < N;
+//   mode 1 (band)    : k in [k0, k1), k <= i < N  (k1 - k0 <= super_tile).
+// fp16 = 1 rounds the panel operands to FP16 (FP32 storage only).
+void launch_update(void *tiles, int store, int b, int64_t N, int64_t p0, int pw, int64_t k0,
+                   int64_t k1, int mode, int super_tile, int fp16, const int64_t *info,
+                   hipStream_t s);
+
+// Triangular solves, in place on B (n x nrhs, ldb), FP64 arithmetic.
+void launch_trsv_fwd(const void *tiles, int store, int b, int64_t N, int64_t n, double *B,
+                     int64_t ldb, int64_t nrhs, hipStream_t s);
+void launch_trsv_bwd(const void *tiles, int store, int b, int64_t N, int64_t n, double *B,
+                     int64_t ldb, int64_t nrhs, hipStream_t s);
+// Scale B by alpha in place (used by the scaled-FP16 factor).
+void launch_scale(double *B, int64_t n, int64_t ldb, int64_t nrhs, double alpha, hipStream_t s);
+
+// R = B - A X, A symmetric from its lower triangle.
+void launch_symm_residual(const double *A, int64_t lda, int64_t n, const double *X,
+                          int64_t ldx, const double *B, int64_t ldb, double *R, int64_t ldr,
+                          int64_t nrhs, hipStream_t s);
+// Per-column squared 2-norms and dot products into out[nrhs] (deterministic).
+void launch_col_dot(const double *x, int64_t ldx, const double *y, int64_t ldy, int64_t n,
+                    int64_t nrhs, double *out, double *partial, hipStream_t s);
+// y[:, c] = a[c] * x[:, c] + b[c] * y[:, c]   (coefficients from device arrays,
+// with per-column active mask; NULL coefficient array means 1).
+void launch_axpby(const double *x, int64_t ldx, double *y, int64_t ldy, int64_t n,
+                  int64_t nrhs, const double *a, double a_sign, const double *bcoef,
+                  const int32_t *active, hipStream_t s);
+// copy n x nrhs column-major blocks
+void launch_copy(const double *x, int64_t ldx, double *y, int64_t ldy, int64_t n,
+                 int64_t nrhs, hipStream_t s);
+
+}  // namespace chol

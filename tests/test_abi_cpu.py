@@ -1,0 +1,89 @@
+"""CPU-side checks of the C ABI: the library loads, exports every function
+declared in include/chol.h, and its host-only entry points (sizes, options,
+status strings, argument validation before any device work) behave."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_2605_13209_amd as P
+from paper_2605_13209_amd import _native
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    text = open(os.path.join(ROOT, "include", "chol.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^[A-Za-z_][\w\s\*]*?\b([a-z_][a-z0-9_]*)\s*\(", text, flags=re.M)
+    return sorted(set(n for n in names if n not in ("if", "sizeof")))
+
+
+def test_header_parsed():
+    names = header_functions()
+    for must in ("gp_assemble", "chol_factor", "chol_solve", "chol_refine_solve", "chol_factor_bytes"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(_native.LIB_PATH)
+    missing = [n for n in header_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+    # and the binding declares every one of them
+    assert set(header_functions()) <= set(_native.EXPORTS)
+
+
+def test_factor_bytes():
+    # packed lower tiles: N(N+1)/2 tiles + 256-byte header
+    assert P.chol_factor_bytes(1024, "fp64", 128) == 256 + 36 * 128 * 128 * 8
+    assert P.chol_factor_bytes(1000, "fp32", 128) == 256 + 36 * 128 * 128 * 4
+    assert P.chol_factor_bytes(65536, "fp64", 128) == 256 + (512 * 513 // 2) * 128 * 128 * 8
+    assert P.chol_factor_bytes(0, "fp64", 64) == 256
+    assert P.chol_factor_bytes(10, "fp64", 96) == 0
+    assert P.chol_factor_bytes(-1, "fp64", 64) == 0
+    assert P.chol_tile_default(200) == 64 and P.chol_tile_default(4096) == 128
+
+
+def test_options_roundtrip_and_validation():
+    old = P.get_option("panel_width")
+    P.set_option("panel_width", 4)
+    assert P.get_option("panel_width") == 4
+    P.set_option("panel_width", old)
+    with pytest.raises(P.CholError):
+        P.set_option("panel_width", 0)
+    with pytest.raises(P.CholError):
+        P.set_option("no_such_knob", 1)
+    assert P.get_option("no_such_knob") == -1
+
+
+def test_status_strings():
+    assert P.chol_status_string(0) == "success"
+    assert P.chol_status_string(-103) == "matrix is not positive definite"
+    assert P.chol_status_string(-3) == "invalid argument"
+
+
+def test_argument_validation_without_device():
+    lib = P.lib()
+    h = ctypes.c_void_p()
+    # n < 0, bad lda, bad precision, bad tile: rejected before any device call
+    assert lib.chol_factor(None, -1, 1, 0, 64, None, 0, ctypes.byref(h), None, None) == -2
+    assert lib.chol_factor(ctypes.c_void_p(256), 10, 5, 0, 64, None, 0, ctypes.byref(h), None, None) == -3
+    assert lib.chol_factor(ctypes.c_void_p(256), 10, 10, 7, 64, None, 0, ctypes.byref(h), None, None) == -4
+    assert lib.chol_factor(ctypes.c_void_p(256), 10, 10, 0, 96, None, 0, ctypes.byref(h), None, None) == -5
+    assert lib.chol_factor(ctypes.c_void_p(256), 10, 10, 0, 64, ctypes.c_void_p(257), 1 << 20,
+                           ctypes.byref(h), None, None) == -6
+    assert lib.chol_factor(ctypes.c_void_p(256), 10, 10, 0, 64, ctypes.c_void_p(512), 16,
+                           ctypes.byref(h), None, None) == -101
+    assert lib.gp_assemble(ctypes.c_void_p(256), 10, 0, 8, 1.0, 1.0, 0.1, ctypes.c_void_p(256), 10, 1, None) == -3
+    assert lib.gp_assemble(ctypes.c_void_p(256), 10, 8, 8, 0.0, 1.0, 0.1, ctypes.c_void_p(256), 10, 1, None) == -5
+    assert lib.gp_assemble(ctypes.c_void_p(256), 10, 8, 8, 1.0, 1.0, 0.1, ctypes.c_void_p(256), 9, 1, None) == -9
+    assert lib.chol_solve(None, None, 1, 1, None) == -105
+    assert lib.chol_refine_bytes(100, 2, 0) == 2 * 100 * 2 * 8 + (8 + 128) * 2 * 8 + 256
+
+
+def test_product_path_fails_loudly_without_library(monkeypatch):
+    monkeypatch.setattr(_native, "_lib", None)
+    monkeypatch.setattr(_native, "LIB_PATH", "/nonexistent/libchol_mi355x.so")
+    with pytest.raises(RuntimeError, match="not built"):
+        _native.lib()

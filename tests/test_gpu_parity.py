@@ -1,0 +1,270 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Tolerances (derivations in DESIGN.md, "Parity bar"):
+* integer / exact-arithmetic cases (known L0): bit-exact;
+* GP assembly: entries within 4 ulp (only exp differs; sums are unfused);
+* FP64 factor: backward error ||A - L L^T||_F / ||A||_F <= 1e-12, and the
+  factor within 1e-11 relative (Frobenius) of the oracle's;
+* FP64 solve: relative error <= 1e-10 against the oracle solve;
+* mixed precision + refinement: relative error <= 1e-10 against the oracle's
+  refined FP64 solution, and certified by ||r|| / (noise ||x||).
+"""
+import numpy as np
+import pytest
+import torch
+
+import gp_inputs
+import oracle
+import paper_2605_13209_amd as P
+
+pytestmark = pytest.mark.gpu
+U = np.finfo(np.float64).eps / 2
+
+
+def dev(a):
+    return P.to_colmajor(torch.from_numpy(np.asarray(a)))
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def gpu_factor_dense(A_np, precision="fp64", tile=0):
+    A = dev(A_np)
+    F = P.chol_factor(A, precision, tile)
+    L = host(P.chol_factor_to_dense(F))
+    return F, L
+
+
+# ------------------------------------------------------------- assembly ---
+
+@pytest.mark.parametrize("n,d,hp", [(1, 8, (1.0, 1.0, 0.1)), (300, 8, (1.0, 1.0, 0.1)),
+                                    (257, 3, (0.5, 2.0, 1.0)), (130, 20, (2.0, 1.0, 0.01))])
+def test_gp_assemble_matches_oracle(n, d, hp):
+    X, _ = gp_inputs.gp_problem(n, d=d, seed=n)
+    ref = oracle.gp_assemble(X, *hp)
+    A = host(P.gp_assemble(torch.from_numpy(X).cuda(), *hp, full=True))
+    assert np.array_equal(A, A.T)
+    assert np.all(np.diag(A) == hp[1] + hp[2])
+    np.testing.assert_allclose(A, ref, rtol=4 * U * 2, atol=0)
+
+
+def test_gp_assemble_lower_only_leaves_upper():
+    n = 200
+    X, _ = gp_inputs.gp_problem(n, seed=1)
+    A = P.colmajor_empty(n, n)
+    A.fill_(-7.0)
+    P.gp_assemble(torch.from_numpy(X).cuda(), 1.0, 1.0, 0.1, full=False, out=A)
+    a = host(A)
+    iu = np.triu_indices(n, 1)
+    assert np.all(a[iu] == -7.0)
+    ref = oracle.gp_assemble(X, 1.0, 1.0, 0.1)
+    il = np.tril_indices(n)
+    np.testing.assert_allclose(a[il], ref[il], rtol=8 * U, atol=0)
+
+
+# ----------------------------------------------------- exact known-L0 ---
+
+@pytest.mark.parametrize("n,tile,family", [(64 * 3 + 17, 64, "dense-int"), (128 * 5 + 3, 128, "dense-int"),
+                                           (777, 128, "sparse-dd"), (256, 128, "dense-int"), (1, 64, "dense-int")])
+def test_known_l0_exact_fp64(n, tile, family):
+    L0, A = gp_inputs.known_l0(n, family, seed=n)
+    F, L = gpu_factor_dense(A, "fp64", tile)
+    assert F.info() == 0
+    np.testing.assert_array_equal(L, L0)
+    F.free()
+
+
+@pytest.mark.parametrize("n,tile", [(300, 64), (700, 128)])
+def test_known_l0_exact_fp32(n, tile):
+    L0, A = gp_inputs.known_l0(n, "small-int", seed=n)
+    assert np.abs(A).max() < 2**24
+    _, L = gpu_factor_dense(A, "fp32", tile)
+    np.testing.assert_array_equal(L, L0)
+
+
+def test_known_l0_exact_solve():
+    n = 500
+    L0, A = gp_inputs.known_l0(n, "sparse-dd", seed=3)
+    x0 = np.random.default_rng(2).integers(-3, 4, size=(n, 5)).astype(np.float64)
+    b = A @ x0  # exact integers
+    F = P.chol_factor(dev(A), "fp64", 128)
+    B = dev(b)
+    P.chol_solve(F, B)
+    # forward/back substitution with an exact L0 (diagonal 32) is exact for sparse-dd
+    np.testing.assert_allclose(host(B), x0, rtol=0, atol=1e-12)
+
+
+# -------------------------------------------------------- GP factors ---
+
+@pytest.mark.parametrize("n,tile", [(1024, 128), (1000, 128), (300, 64), (129, 128), (2, 64)])
+def test_fp64_factor_parity(n, tile):
+    X, _ = gp_inputs.gp_problem(n, seed=0)
+    A = oracle.gp_assemble(X, 1.0, 1.0, 0.1)
+    Lref, info = oracle.cholesky(A)
+    assert info == 0
+    F, L = gpu_factor_dense(A, "fp64", tile)
+    assert F.info() == 0
+    assert np.all(np.triu(L, 1) == 0)
+    be = oracle.backward_error(A, L)
+    assert be <= 1e-12, be
+    rel = np.linalg.norm(L - Lref) / np.linalg.norm(Lref)
+    assert rel <= 1e-11, rel
+
+
+@pytest.mark.parametrize("k", [1, 16])
+def test_fp64_solve_parity(k):
+    n = 1024
+    X, B = gp_inputs.gp_problem(n, seed=0, k=k)
+    A = oracle.gp_assemble(X, 1.0, 1.0, 0.1)
+    Lref, _ = oracle.cholesky(A)
+    xref = oracle.solve(Lref, B)
+    F = P.chol_factor(dev(A), "fp64", 128)
+    Bd = dev(B)
+    P.chol_solve(F, Bd)
+    x = host(Bd)
+    for c in range(k):
+        err = np.linalg.norm(x[:, c] - xref[:, c]) / np.linalg.norm(xref[:, c])
+        assert err <= 1e-10, (c, err)
+
+
+@pytest.mark.parametrize("n,tile", [(1000, 128), (333, 64)])
+def test_fp32_factor_backward_error(n, tile):
+    X, _ = gp_inputs.gp_problem(n, seed=5)
+    A = oracle.gp_assemble(X, 1.0, 1.0, 0.1)
+    Lref, _ = oracle.cholesky(A)
+    _, L = gpu_factor_dense(A, "fp32", tile)
+    be = oracle.backward_error(A, L)
+    # FP32 storage and update: backward error of order n u_32 at most
+    assert be <= 5e-6, be
+    assert np.linalg.norm(L - Lref) / np.linalg.norm(Lref) <= 1e-3
+
+
+def test_not_spd_info_matches_oracle():
+    n = 300
+    X, _ = gp_inputs.gp_problem(n, seed=7)
+    A = oracle.gp_assemble(X, 1.0, 1.0, 0.1)
+    A[200, 200] = -5.0
+    _, info_ref = oracle.cholesky(A)
+    assert info_ref == 201
+    for prec, tile in [("fp64", 64), ("fp64", 128), ("fp32", 128)]:
+        F = P.chol_factor(dev(A), prec, tile, sync=False)
+        assert F.info() == info_ref
+        with pytest.raises(P.CholError):
+            P.chol_solve(F, dev(np.ones((n, 1))))
+    A2 = oracle.gp_assemble(X, 1.0, 1.0, 0.1)
+    A2[17, 3] = np.nan
+    _, info2 = oracle.cholesky(A2)
+    F = P.chol_factor(dev(A2), "fp64", 64, sync=False)
+    assert F.info() == info2
+
+
+def test_schedule_invariance_bitwise():
+    """Panel width and lookahead change the schedule, not the arithmetic."""
+    n = 1300
+    X, _ = gp_inputs.gp_problem(n, seed=3)
+    A = dev(oracle.gp_assemble(X, 1.0, 1.0, 0.1))
+    outs = []
+    try:
+        for w, la in [(1, 0), (2, 1), (4, 1), (3, 0)]:
+            P.set_option("panel_width", w)
+            P.set_option("lookahead", la)
+            for prec in ("fp64", "fp32"):
+                F = P.chol_factor(A, prec, 128)
+                outs.append((prec, host(P.chol_factor_to_dense(F))))
+    finally:
+        P.set_option("panel_width", 2)
+        P.set_option("lookahead", 1)
+    for prec in ("fp64", "fp32"):
+        ref = [L for p, L in outs if p == prec]
+        for L in ref[1:]:
+            assert np.array_equal(L, ref[0])
+
+
+def test_repeatable_bitwise():
+    n = 900
+    X, _ = gp_inputs.gp_problem(n, seed=4)
+    A = dev(oracle.gp_assemble(X, 1.0, 1.0, 0.1))
+    L1 = host(P.chol_factor_to_dense(P.chol_factor(A, "fp64", 128)))
+    L2 = host(P.chol_factor_to_dense(P.chol_factor(A, "fp64", 128)))
+    assert np.array_equal(L1, L2)
+
+
+# ------------------------------------------------------------ residual ---
+
+@pytest.mark.parametrize("k", [1, 3, 9])
+def test_residual_matches_oracle(k):
+    n = 517
+    X, B = gp_inputs.gp_problem(n, seed=9, k=k)
+    A = oracle.gp_assemble(X, 1.0, 1.0, 0.1)
+    xs = np.asfortranarray(np.random.default_rng(1).standard_normal((n, k)))
+    ref = oracle.residual(A, xs, B)
+    Ad = dev(A)
+    # lower triangle only is read: poison the upper part
+    a = Ad.clone()
+    iu = torch.triu_indices(n, n, 1)
+    a[iu[0], iu[1]] = float("nan")
+    R = host(P.chol_residual(a, dev(xs), dev(B)))
+    scale = np.abs(A) @ np.abs(xs) + np.abs(B)
+    assert np.all(np.abs(R - ref) <= 4 * U * scale)
+
+
+# ------------------------------------------------- mixed precision + IR ---
+
+@pytest.mark.parametrize("method", ["ir", "pcg"])
+@pytest.mark.parametrize("matrix_free", [False, True])
+def test_fp32_refine_parity(method, matrix_free):
+    n, k = 1024, 3
+    X, B = gp_inputs.gp_problem(n, seed=0, k=k)
+    A = oracle.gp_assemble(X, 1.0, 1.0, 0.1)
+    Lref, _ = oracle.cholesky(A)
+    xref, _, _, failed = oracle.refine(Lref, A, B, lam=0.1, tol=1e-13)
+    assert failed == 0
+    Xd = torch.from_numpy(X).cuda()
+    Ad = P.gp_assemble(Xd, 1.0, 1.0, 0.1)
+    F = P.chol_factor(Ad, "fp32", 128)
+    kw = dict(X_feat=Xd) if matrix_free else dict(A=Ad)
+    res = P.chol_refine_solve(F, dev(B), lengthscale=1.0, variance=1.0, noise=0.1, tol=1e-10,
+                              method=method, **kw)
+    assert res.converged and res.cert <= 0.5e-10
+    assert res.iters >= 1
+    x = host(res.X)
+    for c in range(k):
+        err = np.linalg.norm(x[:, c] - xref[:, c]) / np.linalg.norm(xref[:, c])
+        assert err <= 1e-10, (c, err)
+        # the reported certificate bounds the true error
+        r = oracle.residual(A, x[:, c], B[:, c])
+        assert oracle.certificate(r, x[:, c], 0.1) <= 1e-10
+
+
+def test_fp64_refine_converges_immediately():
+    n = 600
+    X, B = gp_inputs.gp_problem(n, seed=2, k=2)
+    Xd = torch.from_numpy(X).cuda()
+    Ad = P.gp_assemble(Xd, 1.0, 1.0, 0.1)
+    F = P.chol_factor(Ad, "fp64", 128)
+    res = P.chol_refine_solve(F, dev(B), A=Ad, noise=0.1, tol=1e-10)
+    assert res.converged and res.iters == 0
+
+
+# ----------------------------------------------------------- edge cases ---
+
+def test_empty_and_tiny():
+    F = P.chol_factor(P.colmajor_empty(0, 0), "fp64", 64)
+    assert F.info() == 0 and F.n == 0
+    A = dev(np.array([[4.0]]))
+    F = P.chol_factor(A, "fp64", 64)
+    L = host(P.chol_factor_to_dense(F))
+    assert L[0, 0] == 2.0
+    B = dev(np.array([[6.0, -2.0]]))
+    P.chol_solve(F, B)
+    np.testing.assert_array_equal(host(B), [[1.5, -0.5]])
+
+
+def test_workspace_too_small_rejected():
+    A = dev(np.eye(100))
+    need = P.chol_factor_bytes(100, "fp64", 64)
+    ws = torch.empty(need - 1, dtype=torch.uint8, device="cuda")
+    with pytest.raises(P.CholError) as e:
+        P.chol_factor(A, "fp64", 64, workspace=ws)
+    assert e.value.status == -101
