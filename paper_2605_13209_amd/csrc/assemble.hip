@@ -18,10 +18,10 @@ namespace {
 constexpr int kAsmTile = 64;   // 64 x 64 output block per workgroup
 constexpr int kFeatChunk = 16; // features staged through LDS per pass
 
-// Squared distance of two feature rows staged in LDS, no contraction.
-__device__ inline double sqdist(const double *xi, const double *xj, int d) {
+// Continue the squared distance s over d more features staged in LDS, in
+// feature order, without contraction.
+__device__ inline double sqdist(double s, const double *xi, const double *xj, int d) {
 #pragma clang fp contract(off)
-  double s = 0.0;
   for (int k = 0; k < d; ++k) {
     const double t = xi[k] - xj[k];
     s += t * t;
@@ -60,10 +60,9 @@ __global__ __launch_bounds__(256) void gp_assemble_kernel(const double *__restri
     __syncthreads();
 #pragma unroll
     for (int m = 0; m < 16; ++m) {
-      s[m] = s[m] + sqdist(&xi[r][0], &xj[cg + 4 * m][0], fc);
+      s[m] = sqdist(s[m], &xi[r][0], &xj[cg + 4 * m][0], fc);
     }
   }
-  // Summing per feature chunk regroups the sum only when d > 16.
   const int64_t i = i0 + r;
   if (i >= n) return;
 #pragma unroll

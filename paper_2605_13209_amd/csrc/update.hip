@@ -16,8 +16,9 @@
 // * Rows are interleaved across the 4 MFMA blocks of a wave (block s takes
 //   rows 4q+s), so a lane's four A (or B) fragments are four consecutive
 //   elements in LDS (one or two ds_read_b128), and a lane's 64 accumulator
-//   values are a 16 x 4 sub-block of C whose columns are 16 contiguous
-//   elements (vector loads/stores of C straight to and from HBM).
+//   values form runs of 4 contiguous elements of C columns (vector
+//   loads/stores of C straight to and from HBM; the 4 lanes sharing a column
+//   cover 128 contiguous bytes).
 // * The panel is streamed through LDS in chunks of KC columns (128 bytes per
 //   tile row), double-buffered; global loads of chunk s+1 are in flight while
 //   chunk s is multiplied.  LDS rows are padded to avoid bank conflicts.
@@ -99,18 +100,22 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void u
 
   T *C = tiles + tile_index(i, k, N) * (int64_t)(BT * BT);
 
-  // Accumulators start as C: acc[s][u][e] <-> C row 64wm+16g+4e+s, col 64wn+4q+u.
+  // Accumulators start as C.  acc[s][u][e] <-> C column 64wn+4q+u and row
+  //   FP32: 64wm + 16g + 4e + s  (16x16x4 f32 output: lane (g,q) reg e = row 4g+e)
+  //   FP64: 64wm + 16e + 4g + s  (16x16x4 f64 output: lane (g,q) reg e = row g+4e)
+  // so each (u, e) group of 4 consecutive s is one contiguous run in memory.
   acc_t acc[4][4];
-  {
-    const int r0 = 64 * wm + 16 * g;
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const T *src = C + (64 * wn + 4 * q + u) * BT + r0;
-      T v[16];
+  for (int u = 0; u < 4; ++u) {
+    const T *col = C + (64 * wn + 4 * q + u) * BT + 64 * wm;
 #pragma unroll
-      for (int x = 0; x < 16 / VE; ++x) *(uint4 *)&v[x * VE] = *(const uint4 *)(src + x * VE);
+    for (int e = 0; e < 4; ++e) {
+      const int r = (MODE == 0) ? 16 * e + 4 * g : 16 * g + 4 * e;
+      T v[4];
 #pragma unroll
-      for (int rho = 0; rho < 16; ++rho) acc[rho & 3][u][rho >> 2] = v[rho];
+      for (int x = 0; x < 4 / VE; ++x) *(uint4 *)&v[x * VE] = *(const uint4 *)(col + r + x * VE);
+#pragma unroll
+      for (int s4 = 0; s4 < 4; ++s4) acc[s4][u][e] = v[s4];
     }
   }
 
@@ -174,16 +179,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void u
     __syncthreads();
   }
 
-  {
-    const int r0 = 64 * wm + 16 * g;
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      T *dst = C + (64 * wn + 4 * q + u) * BT + r0;
-      T v[16];
+  for (int u = 0; u < 4; ++u) {
+    T *col = C + (64 * wn + 4 * q + u) * BT + 64 * wm;
 #pragma unroll
-      for (int rho = 0; rho < 16; ++rho) v[rho] = acc[rho & 3][u][rho >> 2];
+    for (int e = 0; e < 4; ++e) {
+      const int r = (MODE == 0) ? 16 * e + 4 * g : 16 * g + 4 * e;
+      T v[4];
 #pragma unroll
-      for (int x = 0; x < 16 / VE; ++x) *(uint4 *)(dst + x * VE) = *(const uint4 *)&v[x * VE];
+      for (int s4 = 0; s4 < 4; ++s4) v[s4] = acc[s4][u][e];
+#pragma unroll
+      for (int x = 0; x < 4 / VE; ++x) *(uint4 *)(col + r + x * VE) = *(const uint4 *)&v[x * VE];
     }
   }
 }

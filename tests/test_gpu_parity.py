@@ -149,7 +149,7 @@ def test_not_spd_info_matches_oracle():
     assert info_ref == 201
     for prec, tile in [("fp64", 64), ("fp64", 128), ("fp32", 128)]:
         F = P.chol_factor(dev(A), prec, tile, sync=False)
-        assert F.info() == info_ref
+        assert F.info() == info_ref, (prec, tile, F.info())
         with pytest.raises(P.CholError):
             P.chol_solve(F, dev(np.ones((n, 1))))
     A2 = oracle.gp_assemble(X, 1.0, 1.0, 0.1)
