@@ -98,7 +98,8 @@ int gp_assemble(const double *X, int64_t n, int64_t d, int64_t ldx,
  * Device workspace, in bytes, that chol_factor needs for an order-n matrix
  * at the given precision and tile (tile 0 = the tuned default).  The factor
  * is stored as the paper stores it (Implementation section): only the
- * lower-triangular and diagonal square blocks, each block contiguous.
+ * lower-triangular and diagonal square blocks, each block contiguous, plus
+ * a transposed copy of the N diagonal blocks for the back substitution.
  * Returns 0 for invalid arguments.  Host-only; no device work.           */
 size_t chol_factor_bytes(int64_t n, int precision, int tile);
 
@@ -213,7 +214,8 @@ void chol_profile_reset(void);
 
 /* ---- tuning knobs (process-wide; set before factorising) ---------------
  * "panel_width"  : tiles per outer step whose Step-3 update is applied in
- *                  one pass (1..8, default 2).
+ *                  one pass (1..8; 0 = automatic: 4 when the matrix has at
+ *                  least 64 tile rows, else 2; default 0).
  * "lookahead"    : 1 overlaps the next panel's Steps 1-2 with the current
  *                  trailing update on a second stream (default 1).
  * "super_tile"   : side, in tiles, of the groups the trailing-update grid

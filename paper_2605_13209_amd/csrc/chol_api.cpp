@@ -34,7 +34,7 @@ namespace {
 constexpr size_t kHeader = 256;  // info word + reserved, at the start of the workspace
 
 struct Options {
-  std::atomic<int64_t> panel_width{2};
+  std::atomic<int64_t> panel_width{0};  // 0: automatic
   std::atomic<int64_t> lookahead{1};
   std::atomic<int64_t> super_tile{8};
   std::atomic<int64_t> graph{0};
@@ -134,6 +134,7 @@ struct chol_factor_s {
   int64_t n = 0, N = 0;
   int b = 0, precision = 0, device = 0;
   void *tiles = nullptr;
+  void *diag_t = nullptr;  // transposed diagonal blocks (back substitution)
   int64_t *d_info = nullptr;
   double scale = 1.0;  // CHOL_FP16_SCALED: the factor of A / scale is stored
   hipStream_t stream = nullptr;
@@ -165,7 +166,7 @@ const char *chol_status_string(int status) {
 int chol_set_option(const char *key, int64_t value) {
   if (!key) return -1;
   if (!strcmp(key, "panel_width")) {
-    if (value < 1 || value > 8) return -2;
+    if (value < 0 || value > 8) return -2;
     g_opt.panel_width = value;
   } else if (!strcmp(key, "lookahead")) {
     if (value < 0 || value > 1) return -2;
@@ -234,7 +235,9 @@ size_t chol_factor_bytes(int64_t n, int precision, int tile) {
   if (tile == 0) tile = chol_tile_default(n, precision);
   if (!tile_ok(tile)) return 0;
   const int64_t N = (n + tile - 1) / tile;
-  return kHeader + (size_t)tile_count(N) * (size_t)tile * (size_t)tile * esize_of(precision);
+  // packed lower tiles, then the N transposed diagonal blocks
+  return kHeader +
+         (size_t)(tile_count(N) + N) * (size_t)tile * (size_t)tile * esize_of(precision);
 }
 
 int gp_assemble(const double *X, int64_t n, int64_t d, int64_t ldx, double lengthscale,
@@ -261,7 +264,7 @@ static void factor_panel(chol_factor_s *F, int64_t c0, int64_t c1, int st, hipSt
   const int b = F->b;
   const int fp16 = F->precision == CHOL_FP16_SCALED;
   for (int64_t c = c0; c < c1; ++c) {
-    launch_potrf(F->tiles, st, b, N, c, F->d_info, s);
+    launch_potrf(F->tiles, st, b, N, c, F->diag_t, F->d_info, s);
     launch_trsm(F->tiles, st, b, N, c, F->d_info, s);
     if (c + 1 < c1)
       update(F->tiles, st, b, N, c, 1, c + 1, c1, /*band*/ 1, 8, fp16, F->d_info, s);
@@ -295,6 +298,7 @@ int chol_factor(const double *A, int64_t n, int64_t lda, int precision, int tile
   (void)hipGetDevice(&F->device);
   F->d_info = (int64_t *)workspace;
   F->tiles = (char *)workspace + kHeader;
+  F->diag_t = (char *)F->tiles + (size_t)tile_count(F->N) * (size_t)tile * tile * esize_of(precision);
   F->stream = (hipStream_t)stream;
   const int st = store_of(precision);
   const int64_t N = F->N;
@@ -319,7 +323,8 @@ int chol_factor(const double *A, int64_t n, int64_t lda, int precision, int tile
   launch_clear_i64(F->d_info, 1, s);
   launch_pack(A, n, lda, F->tiles, st, b, N, pack_scale, s);
 
-  const int64_t w = g_opt.panel_width;
+  // panel width: tile columns per Step-3 pass over the far trailing matrix
+  const int64_t w = g_opt.panel_width > 0 ? (int64_t)g_opt.panel_width : (N >= 64 ? 4 : 2);
   const int S = (int)g_opt.super_tile;
   const int fp16 = precision == CHOL_FP16_SCALED;
   const bool la = g_opt.lookahead != 0 && N > w;
@@ -396,7 +401,7 @@ int chol_solve(chol_handle F, double *B, int64_t nrhs, int64_t ldb, void *stream
   hipStream_t s = (hipStream_t)stream;
   const int st = store_of(F->precision);
   launch_trsv_fwd(F->tiles, st, F->b, F->N, F->n, B, ldb, nrhs, s);
-  launch_trsv_bwd(F->tiles, st, F->b, F->N, F->n, B, ldb, nrhs, s);
+  launch_trsv_bwd(F->tiles, F->diag_t, st, F->b, F->N, F->n, B, ldb, nrhs, s);
   if (F->scale != 1.0) launch_scale(B, F->n, ldb, nrhs, 1.0 / F->scale, s);
   return hipGetLastError() == hipSuccess ? CHOL_OK : CHOL_ERR_HIP;
 }

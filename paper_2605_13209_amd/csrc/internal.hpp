@@ -29,11 +29,11 @@ enum Store : int { STORE_F64 = 0, STORE_F32 = 1 };
 
 // ---- launchers (all asynchronous on `s`) --------------------------------
 // gp_assemble into a column-major matrix.
-void launch_gp_assemble(const double *X, int64_t n, int64_t d, int64_t ldx, double inv2l2,
+void launch_gp_assemble(const double *X, int64_t n, int64_t d, int64_t ldx, double two_l2,
                         double var, double noise, double *A, int64_t lda, int full,
                         hipStream_t s);
 // Matrix-free GP residual R = B - (K + noise I) Xs.
-void launch_gp_residual(const double *F, int64_t n, int64_t d, int64_t ldf, double inv2l2,
+void launch_gp_residual(const double *F, int64_t n, int64_t d, int64_t ldf, double two_l2,
                         double var, double noise, const double *Xs, int64_t ldxs,
                         const double *B, int64_t ldb, double *R, int64_t ldr, int64_t nrhs,
                         hipStream_t s);
@@ -48,9 +48,10 @@ void launch_pack(const double *A, int64_t n, int64_t lda, void *tiles, int store
 void launch_unpack(const void *tiles, int store, int b, int64_t N, int64_t n, double scale,
                    double *L, int64_t ldl, hipStream_t s);
 
-// Step 1: factor diagonal tile c in place (FP64 arithmetic).  Sets *info.
-void launch_potrf(void *tiles, int store, int b, int64_t N, int64_t c, int64_t *info,
-                  hipStream_t s);
+// Step 1: factor diagonal tile c in place (FP64 arithmetic) and store its
+// transpose as block c of diag_t (N blocks of b x b).  Sets *info.
+void launch_potrf(void *tiles, int store, int b, int64_t N, int64_t c, void *diag_t,
+                  int64_t *info, hipStream_t s);
 // Step 2: tiles (i, c), i in [c+1, N): X <- X L_cc^{-T} (FP64 arithmetic).
 void launch_trsm(void *tiles, int store, int b, int64_t N, int64_t c, const int64_t *info,
                  hipStream_t s);
@@ -62,11 +63,12 @@ void launch_update(void *tiles, int store, int b, int64_t N, int64_t p0, int pw,
                    int64_t k1, int mode, int super_tile, int fp16, const int64_t *info,
                    hipStream_t s);
 
-// Triangular solves, in place on B (n x nrhs, ldb), FP64 arithmetic.
+// Triangular solves, in place on B (n x nrhs, ldb), FP64 arithmetic.  The
+// back substitution reads the transposed diagonal blocks from diag_t.
 void launch_trsv_fwd(const void *tiles, int store, int b, int64_t N, int64_t n, double *B,
                      int64_t ldb, int64_t nrhs, hipStream_t s);
-void launch_trsv_bwd(const void *tiles, int store, int b, int64_t N, int64_t n, double *B,
-                     int64_t ldb, int64_t nrhs, hipStream_t s);
+void launch_trsv_bwd(const void *tiles, const void *diag_t, int store, int b, int64_t N,
+                     int64_t n, double *B, int64_t ldb, int64_t nrhs, hipStream_t s);
 // Scale B by alpha in place (used by the scaled-FP16 factor).
 void launch_scale(double *B, int64_t n, int64_t ldb, int64_t nrhs, double alpha, hipStream_t s);
 

@@ -13,96 +13,181 @@ namespace chol {
 namespace {
 
 // ---------------------------------------------------------------- Step 1 --
-// One workgroup of 256 threads factors a B x B diagonal tile held in LDS as
-// FP64 (column-major, pitch B + 1).  Right-looking, unblocked: for each
-// column k the pivot is checked, the column below it is divided by sqrt of
-// the pivot, and the trailing lower triangle receives the rank-1 update.
-// Thread t owns row k+1+(t mod B) of the trailing block and every
-// (256/B)-th column of it, so a wave touches consecutive rows of one column
-// (bank-conflict free) and reads L_jk as a broadcast.
+// One workgroup of 256 threads factors a B x B diagonal tile (B = 16 M) held
+// in registers as FP64.  Threads form a 16 x 16 grid; thread (tr, tc) owns
+// the elements (tr + 16 m, tc + 16 n), m, n < M (a cyclic distribution, so the
+// shrinking trailing triangle stays spread over all threads).  Right-looking,
+// one column k per step:
+//   (1) the owner of (k, k) publishes the pivot;            barrier
+//   (2) everyone checks it (uniform exit on failure); the owners of column k
+//       divide it by sqrt(pivot) and publish it;           barrier
+//   (3) every thread applies the rank-1 update to its trailing elements.
+// Register indices are compile-time: the column loop is split into an
+// unrolled block index km and a runtime offset kr (k = 16 km + kr), and the
+// blocks that are inactive at block km are skipped at compile time.  The tile
+// is moved between HBM and registers through LDS so that the global accesses
+// are contiguous columns.  The kernel also stores L_cc^T (column-major) in a
+// side array, so that the back substitution reads the diagonal blocks along
+// columns as well.
 template <int B, typename T>
 __global__ __launch_bounds__(256) void potrf_kernel(T *__restrict__ tiles, int64_t N, int64_t c,
+                                                    T *__restrict__ diag_t,
                                                     int64_t *__restrict__ info) {
   if (*info != 0) return;
+  constexpr int M = B / 16;
   constexpr int LD = B + 1;
-  constexpr int JS = 256 / B;  // column stride of a thread in the trailing update
-  __shared__ double a[B * LD];
+  __shared__ double stage[B * LD];
+  __shared__ double col[B];
+  __shared__ double piv;
   T *tile = tiles + tile_index(c, c, N) * (int64_t)(B * B);
-  const int t = threadIdx.x;
+  const int t = threadIdx.x, tc = t & 15, tr = t >> 4;
   for (int e = t; e < B * B; e += 256) {
     const int r = e % B, cc = e / B;
-    a[cc * LD + r] = (r >= cc) ? (double)tile[e] : 0.0;
+    stage[cc * LD + r] = (double)tile[e];
   }
   __syncthreads();
-  const int ri = t % B, jg = t / B;
-  for (int k = 0; k < B; ++k) {
-    const double d = a[k * LD + k];
-    if (!(d > 0.0)) {  // uniform: every thread read the same pivot
-      if (t == 0) *info = c * B + k + 1;
-      return;
+  double a[M][M];
+#pragma unroll
+  for (int m = 0; m < M; ++m)
+#pragma unroll
+    for (int n = 0; n < M; ++n) a[m][n] = stage[(tc + 16 * n) * LD + tr + 16 * m];
+
+#pragma unroll
+  for (int km = 0; km < M; ++km) {
+    for (int kr = 0; kr < 16; ++kr) {
+      const int k = 16 * km + kr;
+      if (tr == kr && tc == kr) piv = a[km][km];
+      __syncthreads();
+      const double d = piv;
+      if (!(d > 0.0)) {  // uniform: every thread read the same pivot
+        if (t == 0) *info = c * B + k + 1;
+        return;
+      }
+      const double lkk = sqrt(d);
+      if (tc == kr) {
+#pragma unroll
+        for (int m = km; m < M; ++m) {
+          const int i = tr + 16 * m;
+          if (i > k) {
+            a[m][km] = a[m][km] / lkk;
+            col[i] = a[m][km];
+          } else if (i == k) {
+            a[m][km] = lkk;
+          }
+        }
+      }
+      __syncthreads();
+      double ci[M], cj[M];
+#pragma unroll
+      for (int m = km; m < M; ++m) {
+        ci[m] = col[tr + 16 * m];
+        cj[m] = col[tc + 16 * m];
+      }
+#pragma unroll
+      for (int m = km; m < M; ++m) {
+#pragma unroll
+        for (int n = km; n <= m; ++n) {
+          const int i = tr + 16 * m, j = tc + 16 * n;
+          if (j > k && i >= j) a[m][n] -= ci[m] * cj[n];
+        }
+      }
     }
-    const double lkk = sqrt(d);
-    __syncthreads();  // all threads hold the pivot before it is overwritten
-    if (t == 0) a[k * LD + k] = lkk;
-    for (int i = k + 1 + t; i < B; i += 256) a[k * LD + i] = a[k * LD + i] / lkk;
-    __syncthreads();
-    const int i = k + 1 + ri;
-    if (i < B) {
-      const double lik = a[k * LD + i];
-      for (int j = k + 1 + jg; j <= i; j += JS) a[j * LD + i] -= lik * a[k * LD + j];
-    }
-    __syncthreads();
   }
+  __syncthreads();
+#pragma unroll
+  for (int m = 0; m < M; ++m)
+#pragma unroll
+    for (int n = 0; n < M; ++n) {
+      const int i = tr + 16 * m, j = tc + 16 * n;
+      stage[j * LD + i] = (i >= j) ? a[m][n] : 0.0;
+    }
+  __syncthreads();
+  T *tt = diag_t + c * (int64_t)(B * B);  // L_cc^T, used by the back substitution
   for (int e = t; e < B * B; e += 256) {
     const int r = e % B, cc = e / B;
-    tile[e] = (T)((r >= cc) ? a[cc * LD + r] : 0.0);
+    tile[e] = (T)stage[cc * LD + r];
+    tt[e] = (T)stage[r * LD + cc];
   }
 }
 
 // ---------------------------------------------------------------- Step 2 --
-// X L^T = A for every tile (i, c), i in [c+1, N).  Each row of X is an
-// independent forward substitution with L = L_cc, so one thread owns one
-// row: workgroup = B threads = one tile.  Columns are processed in blocks of
-// 16 held in registers; earlier solved values are re-read from the tile in
-// global memory (written by the same thread).  L is read with uniform
-// addresses, i.e. as broadcasts.
+// X L^T = A for every tile (i, c), i in [c+1, N): each row of X is an
+// independent forward substitution with L = L_cc.  One workgroup of 256
+// threads per tile; thread (r, h) handles row r (r = t mod B) and owns the
+// column blocks q (16 columns each) with q mod H = h (H = 256 / B), keeping
+// its solved values in registers.  For block q:
+//   the 16-row strip of L needed (rows 16q.., columns < 16q + 16) is staged
+//   in LDS and read as broadcasts;
+//   every thread sums x_m L[16q+u][m] over its own earlier blocks;
+//   the owner of block q adds the H partial sums (in a fixed order) to the
+//   right-hand side and solves the 16 x 16 triangle by substitution.
 template <int B, typename T>
-__global__ __launch_bounds__(B) void trsm_kernel(T *__restrict__ tiles, int64_t N, int64_t c,
-                                                 const int64_t *__restrict__ info) {
+__global__ __launch_bounds__(256) void trsm_kernel(T *__restrict__ tiles, int64_t N, int64_t c,
+                                                   const int64_t *__restrict__ info) {
   if (*info != 0) return;
-  constexpr int CB = 16;
+  constexpr int CB = 16, NB = B / CB, H = 256 / B;
+  __shared__ double ls[B * CB];            // ls[m * CB + u] = L[16q + u][m]
+  __shared__ double part[H][CB][B + 1];    // partial sums per (h, u, row)
   const int64_t i = c + 1 + blockIdx.x;
-  const T *__restrict__ L = tiles + tile_index(c, c, N) * (int64_t)(B * B);
+  const T *L = tiles + tile_index(c, c, N) * (int64_t)(B * B);
   T *X = tiles + tile_index(i, c, N) * (int64_t)(B * B);
-  const int r = threadIdx.x;
-  for (int q = 0; q < B / CB; ++q) {
+  const int t = threadIdx.x, r = t % B, h = t / B;
+  double x[NB / H][CB];
+#pragma unroll
+  for (int q = 0; q < NB; ++q) {
+    __syncthreads();
+    for (int e = t; e < (q + 1) * CB * CB; e += 256) {
+      const int m = e / CB, u = e % CB;
+      ls[m * CB + u] = (double)L[m * B + q * CB + u];
+    }
+    __syncthreads();
     double acc[CB];
 #pragma unroll
-    for (int u = 0; u < CB; ++u) acc[u] = (double)X[(q * CB + u) * B + r];
-    for (int m = 0; m < q * CB; ++m) {
-      const double xm = (double)X[m * B + r];
+    for (int u = 0; u < CB; ++u) acc[u] = 0.0;
 #pragma unroll
-      for (int u = 0; u < CB; ++u) acc[u] -= xm * (double)L[m * B + q * CB + u];
+    for (int qq = 0; qq < q; ++qq) {
+      if (qq % H == h) {
+#pragma unroll
+        for (int mm = 0; mm < CB; ++mm) {
+          const double xm = x[qq / H][mm];
+#pragma unroll
+          for (int u = 0; u < CB; ++u) acc[u] += xm * ls[(qq * CB + mm) * CB + u];
+        }
+      }
     }
 #pragma unroll
-    for (int u = 0; u < CB; ++u) {
+    for (int u = 0; u < CB; ++u) part[h][u][r] = acc[u];
+    __syncthreads();
+    if (h == q % H) {
+      double v[CB];
 #pragma unroll
-      for (int v = 0; v < u; ++v) acc[u] -= acc[v] * (double)L[(q * CB + v) * B + q * CB + u];
-      acc[u] = acc[u] / (double)L[(q * CB + u) * B + q * CB + u];
+      for (int u = 0; u < CB; ++u) {
+        double s = part[0][u][r];
+#pragma unroll
+        for (int hh = 1; hh < H; ++hh) s += part[hh][u][r];
+        v[u] = (double)X[(q * CB + u) * B + r] - s;
+      }
+#pragma unroll
+      for (int u = 0; u < CB; ++u) {
+#pragma unroll
+        for (int w = 0; w < u; ++w) v[u] -= v[w] * ls[(q * CB + w) * CB + u];
+        v[u] = v[u] / ls[(q * CB + u) * CB + u];
+        x[q / H][u] = v[u];
+        X[(q * CB + u) * B + r] = (T)v[u];
+      }
     }
-#pragma unroll
-    for (int u = 0; u < CB; ++u) X[(q * CB + u) * B + r] = (T)acc[u];
   }
 }
 
 template <int B>
-void potrf_dispatch(void *tiles, int store, int64_t N, int64_t c, int64_t *info, hipStream_t s) {
+void potrf_dispatch(void *tiles, int store, int64_t N, int64_t c, void *diag_t, int64_t *info,
+                    hipStream_t s) {
   if (store == STORE_F64)
     hipLaunchKernelGGL((potrf_kernel<B, double>), dim3(1), dim3(256), 0, s, (double *)tiles, N, c,
-                       info);
+                       (double *)diag_t, info);
   else
     hipLaunchKernelGGL((potrf_kernel<B, float>), dim3(1), dim3(256), 0, s, (float *)tiles, N, c,
-                       info);
+                       (float *)diag_t, info);
 }
 
 template <int B>
@@ -111,21 +196,21 @@ void trsm_dispatch(void *tiles, int store, int64_t N, int64_t c, const int64_t *
   const int64_t nt = N - c - 1;
   if (nt <= 0) return;
   if (store == STORE_F64)
-    hipLaunchKernelGGL((trsm_kernel<B, double>), dim3((unsigned)nt), dim3(B), 0, s,
+    hipLaunchKernelGGL((trsm_kernel<B, double>), dim3((unsigned)nt), dim3(256), 0, s,
                        (double *)tiles, N, c, info);
   else
-    hipLaunchKernelGGL((trsm_kernel<B, float>), dim3((unsigned)nt), dim3(B), 0, s, (float *)tiles,
-                       N, c, info);
+    hipLaunchKernelGGL((trsm_kernel<B, float>), dim3((unsigned)nt), dim3(256), 0, s,
+                       (float *)tiles, N, c, info);
 }
 
 }  // namespace
 
-void launch_potrf(void *tiles, int store, int b, int64_t N, int64_t c, int64_t *info,
-                  hipStream_t s) {
+void launch_potrf(void *tiles, int store, int b, int64_t N, int64_t c, void *diag_t,
+                  int64_t *info, hipStream_t s) {
   if (b == 128)
-    potrf_dispatch<128>(tiles, store, N, c, info, s);
+    potrf_dispatch<128>(tiles, store, N, c, diag_t, info, s);
   else
-    potrf_dispatch<64>(tiles, store, N, c, info, s);
+    potrf_dispatch<64>(tiles, store, N, c, diag_t, info, s);
 }
 
 void launch_trsm(void *tiles, int store, int b, int64_t N, int64_t c, const int64_t *info,

@@ -14,8 +14,9 @@
 // The solves are HBM-bound (each tile of L is read once per pass); the
 // diagonal solves are one wave per right-hand side with register-resident
 // rows and lane broadcasts, without workgroup barriers inside the
-// substitution loop.  Padding rows (>= n) are treated as zero and never
-// written, which is exact because the padded factor is diag(L, I).
+// substitution loop (see diag_solve).  Padding rows (>= n) are treated as
+// zero and never written, which is exact because the padded factor is
+// diag(L, I).
 #include "internal.hpp"
 
 namespace chol {
@@ -92,14 +93,23 @@ __device__ void apply_tile(const T *__restrict__ Lt, const double *ysrc_base, in
   }
 }
 
-// Diagonal solve of block row s: L_ss y = b (UPPER = false) or L_ss^T x = y
-// (UPPER = true).  Wave w handles right-hand sides w, w+4, ...; lane l owns
-// rows l, l+64, ... of the block.
+// Diagonal solve of block row s with a column-major triangular block D:
+//   LOWER (forward):  D = L_ss,   solve D y = b  for rows ascending;
+//   UPPER (back):     D = L_ss^T, solve D x = y  for rows descending.
+// Wave w handles right-hand sides w, w+4, ...; lane l owns rows l + 64 j.
+// Step r broadcasts the finished value of row r from its lane (readlane) and
+// updates the other rows with column r of D, which is contiguous in memory;
+// the column values of 8 steps are loaded ahead of their use.  Divisions are
+// multiplications by reciprocals of the diagonal, computed once per lane.
 template <int B, typename T, bool UPPER>
-__device__ void diag_solve(const T *__restrict__ Ld, int64_t row0, double *B_, int64_t ldb,
+__device__ void diag_solve(const T *__restrict__ D, int64_t row0, double *B_, int64_t ldb,
                            int64_t n, int64_t nrhs) {
   constexpr int J = B / 64;
+  constexpr int U = 8;  // steps per prefetch batch
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  double rinv[J];
+#pragma unroll
+  for (int j = 0; j < J; ++j) rinv[j] = 1.0 / (double)D[(lane + 64 * j) * B + lane + 64 * j];
   for (int64_t c = wave; c < nrhs; c += 4) {
     double v[J];
 #pragma unroll
@@ -107,35 +117,29 @@ __device__ void diag_solve(const T *__restrict__ Ld, int64_t row0, double *B_, i
       const int64_t row = row0 + lane + 64 * j;
       v[j] = (row < n) ? B_[row + c * ldb] : 0.0;
     }
-    if constexpr (!UPPER) {
 #pragma unroll
-      for (int jr = 0; jr < J; ++jr) {
-        for (int rr = 0; rr < 64; ++rr) {
-          const int r = 64 * jr + rr;
-          const double yr = readlane_f64(v[jr], rr) / (double)Ld[r * B + r];
+    for (int jj = 0; jj < J; ++jj) {
+      const int jr = UPPER ? J - 1 - jj : jj;  // 64-row block holding the pivot rows
+      for (int b0 = 0; b0 < 64; b0 += U) {
+        double col[U][J];
 #pragma unroll
-          for (int j = 0; j < J; ++j) {
-            const int m = lane + 64 * j;
-            if (m == r)
-              v[j] = yr;
-            else if (m > r)
-              v[j] -= (double)Ld[r * B + m] * yr;
-          }
+        for (int q = 0; q < U; ++q) {
+          const int r = 64 * jr + (UPPER ? 63 - b0 - q : b0 + q);
+#pragma unroll
+          for (int j = 0; j < J; ++j) col[q][j] = (double)D[r * B + lane + 64 * j];
         }
-      }
-    } else {
 #pragma unroll
-      for (int jr = J - 1; jr >= 0; --jr) {
-        for (int rr = 63; rr >= 0; --rr) {
-          const int r = 64 * jr + rr;
-          const double xr = readlane_f64(v[jr], rr) / (double)Ld[r * B + r];
+        for (int q = 0; q < U; ++q) {
+          const int rl = UPPER ? 63 - b0 - q : b0 + q;  // lane holding row r
+          const int r = 64 * jr + rl;
+          const double xr = readlane_f64(v[jr], rl) * readlane_f64(rinv[jr], rl);
 #pragma unroll
           for (int j = 0; j < J; ++j) {
             const int m = lane + 64 * j;
             if (m == r)
               v[j] = xr;
-            else if (m < r)
-              v[j] -= (double)Ld[m * B + r] * xr;
+            else if (UPPER ? (m < r) : (m > r))
+              v[j] -= col[q][j] * xr;
           }
         }
       }
@@ -169,7 +173,8 @@ __global__ __launch_bounds__(256) void trsv_fwd_step(const T *__restrict__ tiles
 }
 
 template <int B, typename T>
-__global__ __launch_bounds__(256) void trsv_bwd_step(const T *__restrict__ tiles, int64_t N,
+__global__ __launch_bounds__(256) void trsv_bwd_step(const T *__restrict__ tiles,
+                                                     const T *__restrict__ diag_t, int64_t N,
                                                      int64_t n, int64_t s, double *B_,
                                                      int64_t ldb, int64_t nrhs) {
   __shared__ double ys[B * NC];
@@ -184,8 +189,7 @@ __global__ __launch_bounds__(256) void trsv_bwd_step(const T *__restrict__ tiles
   if (w == 0) {
     __threadfence_block();
     __syncthreads();
-    diag_solve<B, T, true>(tiles + tile_index(s, s, N) * (int64_t)(B * B), s * B, B_, ldb, n,
-                           nrhs);
+    diag_solve<B, T, true>(diag_t + s * (int64_t)(B * B), s * B, B_, ldb, n, nrhs);
   }
 }
 
@@ -197,8 +201,8 @@ __global__ void scale_kernel(double *B_, int64_t n, int64_t ldb, int64_t nrhs, d
 }
 
 template <int B, typename T>
-void trsv_run(const T *tiles, int64_t N, int64_t n, double *B_, int64_t ldb, int64_t nrhs,
-              bool fwd, hipStream_t st) {
+void trsv_run(const T *tiles, const T *diag_t, int64_t N, int64_t n, double *B_, int64_t ldb,
+              int64_t nrhs, bool fwd, hipStream_t st) {
   if (fwd) {
     for (int64_t s = 0; s < N; ++s) {
       const unsigned grid = (s == 0) ? 1u : (unsigned)(N - s);
@@ -208,25 +212,27 @@ void trsv_run(const T *tiles, int64_t N, int64_t n, double *B_, int64_t ldb, int
   } else {
     for (int64_t s = N - 1; s >= 0; --s) {
       const unsigned grid = (s == N - 1) ? 1u : (unsigned)(s + 1);
-      hipLaunchKernelGGL((trsv_bwd_step<B, T>), dim3(grid), dim3(256), 0, st, tiles, N, n, s, B_,
-                         ldb, nrhs);
+      hipLaunchKernelGGL((trsv_bwd_step<B, T>), dim3(grid), dim3(256), 0, st, tiles, diag_t, N, n,
+                         s, B_, ldb, nrhs);
     }
   }
 }
 
-void trsv_dispatch(const void *tiles, int store, int b, int64_t N, int64_t n, double *B_,
-                   int64_t ldb, int64_t nrhs, bool fwd, hipStream_t st) {
+void trsv_dispatch(const void *tiles, const void *dt, int store, int b, int64_t N, int64_t n,
+                   double *B_, int64_t ldb, int64_t nrhs, bool fwd, hipStream_t st) {
   if (N <= 0 || nrhs <= 0) return;
   if (b == 128) {
     if (store == STORE_F64)
-      trsv_run<128, double>((const double *)tiles, N, n, B_, ldb, nrhs, fwd, st);
+      trsv_run<128, double>((const double *)tiles, (const double *)dt, N, n, B_, ldb, nrhs, fwd,
+                            st);
     else
-      trsv_run<128, float>((const float *)tiles, N, n, B_, ldb, nrhs, fwd, st);
+      trsv_run<128, float>((const float *)tiles, (const float *)dt, N, n, B_, ldb, nrhs, fwd, st);
   } else {
     if (store == STORE_F64)
-      trsv_run<64, double>((const double *)tiles, N, n, B_, ldb, nrhs, fwd, st);
+      trsv_run<64, double>((const double *)tiles, (const double *)dt, N, n, B_, ldb, nrhs, fwd,
+                           st);
     else
-      trsv_run<64, float>((const float *)tiles, N, n, B_, ldb, nrhs, fwd, st);
+      trsv_run<64, float>((const float *)tiles, (const float *)dt, N, n, B_, ldb, nrhs, fwd, st);
   }
 }
 
@@ -234,12 +240,12 @@ void trsv_dispatch(const void *tiles, int store, int b, int64_t N, int64_t n, do
 
 void launch_trsv_fwd(const void *tiles, int store, int b, int64_t N, int64_t n, double *B_,
                      int64_t ldb, int64_t nrhs, hipStream_t s) {
-  trsv_dispatch(tiles, store, b, N, n, B_, ldb, nrhs, true, s);
+  trsv_dispatch(tiles, nullptr, store, b, N, n, B_, ldb, nrhs, true, s);
 }
 
-void launch_trsv_bwd(const void *tiles, int store, int b, int64_t N, int64_t n, double *B_,
-                     int64_t ldb, int64_t nrhs, hipStream_t s) {
-  trsv_dispatch(tiles, store, b, N, n, B_, ldb, nrhs, false, s);
+void launch_trsv_bwd(const void *tiles, const void *diag_t, int store, int b, int64_t N,
+                     int64_t n, double *B_, int64_t ldb, int64_t nrhs, hipStream_t s) {
+  trsv_dispatch(tiles, diag_t, store, b, N, n, B_, ldb, nrhs, false, s);
 }
 
 void launch_scale(double *B_, int64_t n, int64_t ldb, int64_t nrhs, double alpha, hipStream_t s) {

@@ -13,12 +13,11 @@
 //   FP32: v_mfma_f32_16x16x4; FP16 operands: v_mfma_f32_16x16x32_f16).
 //   The accumulators are initialised with the C tile itself and the panel
 //   operand A is negated when staged, so each MFMA performs C -= a b^T.
-// * Rows are interleaved across the 4 MFMA blocks of a wave (block s takes
-//   rows 4q+s), so a lane's four A (or B) fragments are four consecutive
-//   elements in LDS (one or two ds_read_b128), and a lane's 64 accumulator
-//   values form runs of 4 contiguous elements of C columns (vector
-//   loads/stores of C straight to and from HBM; the 4 lanes sharing a column
-//   cover 128 contiguous bytes).
+// * Rows are interleaved across the 4 MFMA blocks of a wave so that a lane's
+//   four A (or B) fragments come from one or two 16-byte LDS reads that are
+//   contiguous across lanes (conflict-free), and a lane's accumulators form
+//   16-byte runs of C columns (vector loads/stores of C straight to and from
+//   HBM).  See the row-interleave comment in update_kernel.
 // * The panel is streamed through LDS in chunks of KC columns (128 bytes per
 //   tile row), double-buffered; global loads of chunk s+1 are in flight while
 //   chunk s is multiplied.  LDS rows are padded to avoid bank conflicts.
@@ -100,23 +99,38 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void u
 
   T *C = tiles + tile_index(i, k, N) * (int64_t)(BT * BT);
 
-  // Accumulators start as C.  acc[s][u][e] <-> C column 64wn+4q+u and row
-  //   FP32: 64wm + 16g + 4e + s  (16x16x4 f32 output: lane (g,q) reg e = row 4g+e)
-  //   FP64: 64wm + 16e + 4g + s  (16x16x4 f64 output: lane (g,q) reg e = row g+4e)
-  // so each (u, e) group of 4 consecutive s is one contiguous run in memory.
+  // Row interleave.  MFMA block s (of 4 per wave and dimension) takes, for
+  // its MFMA row index i, the wave-local row
+  //   FP64: 2i + (s & 1) + 32 (s >> 1)   -> a lane's fragments are rows
+  //         {2q, 2q+1} and {2q+32, 2q+33}: two 16-byte LDS reads that are
+  //         contiguous across the 16 lanes of a group (no bank conflicts);
+  //   FP32: 4i + s                       -> one 16-byte read {4q..4q+3}.
+  // Columns (the B operand) use the same map.  With the MFMA output layouts
+  // (lane (g,q), register e holds MFMA row g+4e for f64, 4g+e for f32, and
+  // MFMA column q), accumulator acc[s][u][e] is C element
+  //   row 64wm + crow(s, e),  column 64wn + ccol(u)
+  // with crow = 2g + 8e + (s&1) + 32(s>>1) (FP64) or 16g + 4e + s (FP32),
+  // ccol = 2q + (u&1) + 32(u>>1) (FP64) or 4q + u (FP32).  Consecutive s
+  // give consecutive rows, so C moves in 16-byte vectors.
+  auto crow = [&](int s4, int e) -> int {
+    return (MODE == 0) ? 2 * g + 8 * e + (s4 & 1) + 32 * (s4 >> 1) : 16 * g + 4 * e + s4;
+  };
+  auto ccol = [&](int u) -> int { return (MODE == 0) ? 2 * q + (u & 1) + 32 * (u >> 1) : 4 * q + u; };
+  constexpr int SPV = (MODE == 0) ? 2 : 4;  // consecutive s per 16-byte vector
+
   acc_t acc[4][4];
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
-    const T *col = C + (64 * wn + 4 * q + u) * BT + 64 * wm;
+    const T *col = C + (64 * wn + ccol(u)) * BT + 64 * wm;
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int r = (MODE == 0) ? 16 * e + 4 * g : 16 * g + 4 * e;
-      T v[4];
+    for (int e = 0; e < 4; ++e)
 #pragma unroll
-      for (int x = 0; x < 4 / VE; ++x) *(uint4 *)&v[x * VE] = *(const uint4 *)(col + r + x * VE);
+      for (int s0 = 0; s0 < 4; s0 += SPV) {
+        T v[SPV];
+        *(uint4 *)&v[0] = *(const uint4 *)(col + crow(s0, e));
 #pragma unroll
-      for (int s4 = 0; s4 < 4; ++s4) acc[s4][u][e] = v[s4];
-    }
+        for (int y = 0; y < SPV; ++y) acc[s0 + y][u][e] = v[y];
+      }
   }
 
   const int nstage = pw * (BT / KC);
@@ -143,6 +157,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void u
       *(uint4 *)&lds[buf][1][kk * LDP + r] = rb[x];
     }
   };
+  // fragments of k-step kk for this lane: a[s], b[u]
+  auto frag = [&](const T *la, const T *lb, int kk, T (&a)[4], T (&b)[4]) {
+    if constexpr (MODE == 0) {
+      *(uint4 *)&a[0] = *(const uint4 *)(la + kk * LDP + 64 * wm + 2 * q);
+      *(uint4 *)&a[2] = *(const uint4 *)(la + kk * LDP + 64 * wm + 2 * q + 32);
+      *(uint4 *)&b[0] = *(const uint4 *)(lb + kk * LDP + 64 * wn + 2 * q);
+      *(uint4 *)&b[2] = *(const uint4 *)(lb + kk * LDP + 64 * wn + 2 * q + 32);
+    } else {
+      *(uint4 *)&a[0] = *(const uint4 *)(la + kk * LDP + 64 * wm + 4 * q);
+      *(uint4 *)&b[0] = *(const uint4 *)(lb + kk * LDP + 64 * wn + 4 * q);
+    }
+  };
 
   gload(0);
   lstore(0);
@@ -152,27 +178,22 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void u
     if (s + 1 < nstage) gload(s + 1);
     const T *la = &lds[buf][0][0];
     const T *lb = &lds[buf][1][0];
+    T a[2][4], b[2][4];
+    frag(la, lb, g, a[0], b[0]);
 #pragma unroll
     for (int ks = 0; ks < KC / 4; ++ks) {
-      const int kk = ks * 4 + g;
-      T a[4], b[4];
-      if constexpr (sizeof(T) == 8) {
-        *(uint4 *)&a[0] = *(const uint4 *)(la + kk * LDP + 64 * wm + 4 * q);
-        *(uint4 *)&a[2] = *(const uint4 *)(la + kk * LDP + 64 * wm + 4 * q + 2);
-        *(uint4 *)&b[0] = *(const uint4 *)(lb + kk * LDP + 64 * wn + 4 * q);
-        *(uint4 *)&b[2] = *(const uint4 *)(lb + kk * LDP + 64 * wn + 4 * q + 2);
-      } else {
-        *(uint4 *)&a[0] = *(const uint4 *)(la + kk * LDP + 64 * wm + 4 * q);
-        *(uint4 *)&b[0] = *(const uint4 *)(lb + kk * LDP + 64 * wn + 4 * q);
-      }
+      const int cur = ks & 1;
+      if (ks + 1 < KC / 4) frag(la, lb, (ks + 1) * 4 + g, a[cur ^ 1], b[cur ^ 1]);
 #pragma unroll
       for (int s2 = 0; s2 < 4; ++s2)
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
           if constexpr (MODE == 0)
-            acc[s2][u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s2], b[u], acc[s2][u], 0, 0, 0);
+            acc[s2][u] =
+                __builtin_amdgcn_mfma_f64_16x16x4f64(a[cur][s2], b[cur][u], acc[s2][u], 0, 0, 0);
           else
-            acc[s2][u] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[s2], b[u], acc[s2][u], 0, 0, 0);
+            acc[s2][u] =
+                __builtin_amdgcn_mfma_f32_16x16x4f32(a[cur][s2], b[cur][u], acc[s2][u], 0, 0, 0);
         }
     }
     if (s + 1 < nstage) lstore(buf ^ 1);
@@ -181,16 +202,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void u
 
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
-    T *col = C + (64 * wn + 4 * q + u) * BT + 64 * wm;
+    T *col = C + (64 * wn + ccol(u)) * BT + 64 * wm;
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int r = (MODE == 0) ? 16 * e + 4 * g : 16 * g + 4 * e;
-      T v[4];
+    for (int e = 0; e < 4; ++e)
 #pragma unroll
-      for (int s4 = 0; s4 < 4; ++s4) v[s4] = acc[s4][u][e];
+      for (int s0 = 0; s0 < 4; s0 += SPV) {
+        T v[SPV];
 #pragma unroll
-      for (int x = 0; x < 4 / VE; ++x) *(uint4 *)(col + r + x * VE) = *(const uint4 *)&v[x * VE];
-    }
+        for (int y = 0; y < SPV; ++y) v[y] = acc[s0 + y][u][e];
+        *(uint4 *)(col + crow(s0, e)) = *(const uint4 *)&v[0];
+      }
   }
 }
 

@@ -35,10 +35,10 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_factor_bytes():
-    # packed lower tiles: N(N+1)/2 tiles + 256-byte header
-    assert P.chol_factor_bytes(1024, "fp64", 128) == 256 + 36 * 128 * 128 * 8
-    assert P.chol_factor_bytes(1000, "fp32", 128) == 256 + 36 * 128 * 128 * 4
-    assert P.chol_factor_bytes(65536, "fp64", 128) == 256 + (512 * 513 // 2) * 128 * 128 * 8
+    # packed lower tiles N(N+1)/2, N transposed diagonal blocks, 256-byte header
+    assert P.chol_factor_bytes(1024, "fp64", 128) == 256 + (36 + 8) * 128 * 128 * 8
+    assert P.chol_factor_bytes(1000, "fp32", 128) == 256 + (36 + 8) * 128 * 128 * 4
+    assert P.chol_factor_bytes(65536, "fp64", 128) == 256 + (512 * 513 // 2 + 512) * 128 * 128 * 8
     assert P.chol_factor_bytes(0, "fp64", 64) == 256
     assert P.chol_factor_bytes(10, "fp64", 96) == 0
     assert P.chol_factor_bytes(-1, "fp64", 64) == 0
@@ -51,7 +51,7 @@ def test_options_roundtrip_and_validation():
     assert P.get_option("panel_width") == 4
     P.set_option("panel_width", old)
     with pytest.raises(P.CholError):
-        P.set_option("panel_width", 0)
+        P.set_option("panel_width", 9)
     with pytest.raises(P.CholError):
         P.set_option("no_such_knob", 1)
     assert P.get_option("no_such_knob") == -1

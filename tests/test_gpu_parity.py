@@ -173,7 +173,7 @@ def test_schedule_invariance_bitwise():
                 F = P.chol_factor(A, prec, 128)
                 outs.append((prec, host(P.chol_factor_to_dense(F))))
     finally:
-        P.set_option("panel_width", 2)
+        P.set_option("panel_width", 0)
         P.set_option("lookahead", 1)
     for prec in ("fp64", "fp32"):
         ref = [L for p, L in outs if p == prec]
