@@ -400,7 +400,7 @@ int chol_solve(chol_handle F, double *B, int64_t nrhs, int64_t ldb, void *stream
   if (F->info > 0) return CHOL_ERR_NOT_SPD;
   hipStream_t s = (hipStream_t)stream;
   const int st = store_of(F->precision);
-  launch_trsv_fwd(F->tiles, st, F->b, F->N, F->n, B, ldb, nrhs, s);
+  launch_trsv_fwd(F->tiles, F->diag_t, st, F->b, F->N, F->n, B, ldb, nrhs, s);
   launch_trsv_bwd(F->tiles, F->diag_t, st, F->b, F->N, F->n, B, ldb, nrhs, s);
   if (F->scale != 1.0) launch_scale(B, F->n, ldb, nrhs, 1.0 / F->scale, s);
   return hipGetLastError() == hipSuccess ? CHOL_OK : CHOL_ERR_HIP;

@@ -65,8 +65,8 @@ void launch_update(void *tiles, int store, int b, int64_t N, int64_t p0, int pw,
 
 // Triangular solves, in place on B (n x nrhs, ldb), FP64 arithmetic.  The
 // back substitution reads the transposed diagonal blocks from diag_t.
-void launch_trsv_fwd(const void *tiles, int store, int b, int64_t N, int64_t n, double *B,
-                     int64_t ldb, int64_t nrhs, hipStream_t s);
+void launch_trsv_fwd(const void *tiles, const void *diag_t, int store, int b, int64_t N,
+                     int64_t n, double *B, int64_t ldb, int64_t nrhs, hipStream_t s);
 void launch_trsv_bwd(const void *tiles, const void *diag_t, int store, int b, int64_t N,
                      int64_t n, double *B, int64_t ldb, int64_t nrhs, hipStream_t s);
 // Scale B by alpha in place (used by the scaled-FP16 factor).
