@@ -215,6 +215,123 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void u
   }
 }
 
+// ---------------------------------------------------------- FP64, 4x4x4 --
+// FP64 update on v_mfma_f64_4x4x4_4b_f64, which on gfx950 sustains the full
+// FP64 matrix rate (the 16x16x4 form issues far less often).  Operand
+// layout of the instruction (lane l = 16 g + q): the lane supplies A[q][g]
+// and B[g][q] of a 16x4 / 4x16 pair, and only the four diagonal 4x4 blocks
+// of the 16x16 product are formed: lane l receives D[4 (q/4) + g][q].  So
+// block bq = q/4 multiplies A-operand rows 4bq..4bq+3 with B-operand
+// columns 4bq..4bq+3.
+//
+// Each wave owns a 64 x 64 block of the 128 x 128 tile and issues, per
+// k-step of 4, 64 instructions (x, y), x < 4, y < 16.  Instruction (x, y)
+// feeds A-operand row i with tile row  rho(x, i) = 2i + (x&1) + 32(x>>1)
+// and B-operand column j with tile column  sigma(y, j) = 4y + (j mod 4).
+// Hence lane (g, q) holds acc[x][y] = C(row 8 bq + 2g + (x&1) + 32(x>>1),
+// column 4y + (q mod 4)), every (row, column) of the 64 x 64 block exactly
+// once; its A fragments are rows {2q, 2q+1} and {2q+32, 2q+33} (two 16-byte
+// LDS reads, contiguous across lanes), its B fragments 16 single elements
+// that four lanes share (broadcast reads), and each C column is touched as
+// two 16-byte vectors.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void update_f64_kernel(
+    double *__restrict__ tiles, int64_t N, int64_t p0, int pw, int64_t k0, int64_t K, int mode,
+    int S, int64_t G, int64_t G8, const int64_t *__restrict__ info) {
+  constexpr int KC = 16;          // panel columns per LDS chunk (128 bytes per tile row)
+  constexpr int LDP = BT + 4;     // LDS row pitch (doubles)
+  constexpr int NV = KC * BT / 2 / 256;  // 16-byte vectors per thread per operand
+  if (*info != 0) return;
+  const int64_t bid = blockIdx.x;
+  const int64_t t = (bid % 8) * G8 + bid / 8;
+  if (t >= G) return;
+  int64_t ir, kr;
+  if (mode == 0)
+    map_triangle(t, N - k0, S, ir, kr);
+  else
+    map_band(t, K, ir, kr);
+  const int64_t i = k0 + ir, k = k0 + kr;
+
+  __shared__ __attribute__((aligned(16))) double lds[2][2][KC * LDP];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int g = lane >> 4, q = lane & 15, bq = q >> 2, jq = q & 3;
+  const int wm = wave >> 1, wn = wave & 1;
+  double *C = tiles + tile_index(i, k, N) * (int64_t)(BT * BT);
+
+  // acc[x][y] <-> C(64wm + 8bq + 2g + (x&1) + 32(x>>1), 64wn + 4y + jq)
+  double acc[4][16];
+#pragma unroll
+  for (int y = 0; y < 16; ++y) {
+    const double *col = C + (64 * wn + 4 * y + jq) * BT + 64 * wm + 8 * bq + 2 * g;
+#pragma unroll
+    for (int xh = 0; xh < 2; ++xh) {
+      double v[2];
+      *(uint4 *)&v[0] = *(const uint4 *)(col + 32 * xh);
+      acc[2 * xh][y] = v[0];
+      acc[2 * xh + 1][y] = v[1];
+    }
+  }
+
+  const int nstage = pw * (BT / KC);
+  uint4 ra[NV], rb[NV];
+  auto gload = [&](int s) {
+    const int64_t p = p0 + (s * KC) / BT;
+    const int col0 = (s * KC) % BT;
+    const double *pa = tiles + tile_index(i, p, N) * (int64_t)(BT * BT) + col0 * BT;
+    const double *pb = tiles + tile_index(k, p, N) * (int64_t)(BT * BT) + col0 * BT;
+#pragma unroll
+    for (int x = 0; x < NV; ++x) {
+      const int v = tid + 256 * x;
+      ra[x] = *(const uint4 *)(pa + v * 2);
+      rb[x] = *(const uint4 *)(pb + v * 2);
+    }
+  };
+  auto lstore = [&](int buf) {
+#pragma unroll
+    for (int x = 0; x < NV; ++x) {
+      const int e = (tid + 256 * x) * 2;
+      const int kk = e / BT, r = e % BT;
+      *(uint4 *)&lds[buf][0][kk * LDP + r] = neg_f64x2(ra[x]);
+      *(uint4 *)&lds[buf][1][kk * LDP + r] = rb[x];
+    }
+  };
+
+  gload(0);
+  lstore(0);
+  __syncthreads();
+  for (int s = 0; s < nstage; ++s) {
+    const int buf = s & 1;
+    if (s + 1 < nstage) gload(s + 1);
+    const double *la = &lds[buf][0][64 * wm + 2 * q];
+    const double *lb = &lds[buf][1][64 * wn + jq];
+#pragma unroll
+    for (int ks = 0; ks < KC / 4; ++ks) {
+      const int kk = ks * 4 + g;
+      double a[4], b[16];
+      *(uint4 *)&a[0] = *(const uint4 *)(la + kk * LDP);
+      *(uint4 *)&a[2] = *(const uint4 *)(la + kk * LDP + 32);
+#pragma unroll
+      for (int y = 0; y < 16; ++y) b[y] = lb[kk * LDP + 4 * y];
+#pragma unroll
+      for (int y = 0; y < 16; ++y)
+#pragma unroll
+        for (int x = 0; x < 4; ++x)
+          acc[x][y] = __builtin_amdgcn_mfma_f64_4x4x4f64(a[x], b[y], acc[x][y], 0, 0, 0);
+    }
+    if (s + 1 < nstage) lstore(buf ^ 1);
+    __syncthreads();
+  }
+
+#pragma unroll
+  for (int y = 0; y < 16; ++y) {
+    double *col = C + (64 * wn + 4 * y + jq) * BT + 64 * wm + 8 * bq + 2 * g;
+#pragma unroll
+    for (int xh = 0; xh < 2; ++xh) {
+      double v[2] = {acc[2 * xh][y], acc[2 * xh + 1][y]};
+      *(uint4 *)(col + 32 * xh) = *(const uint4 *)&v[0];
+    }
+  }
+}
+
 // --------------------------------------------------- FP16 operands (FP32 C) --
 // Panel tiles are FP32 in memory; each chunk is rounded to FP16 when staged.
 // v_mfma_f32_16x16x32_f16: lane (g, q) supplies A[row q][k = 8g .. 8g+7] and
@@ -392,7 +509,7 @@ void launch_update(void *tiles, int store, int b, int64_t N, int64_t p0, int pw,
       hipLaunchKernelGGL(update_f16_kernel, grid, dim3(256), 0, s, (float *)tiles, N, p0, pw, k0,
                          K, mode, super_tile, G, G8, info);
     else if (store == STORE_F64)
-      hipLaunchKernelGGL(update_kernel<0>, grid, dim3(256), 0, s, (double *)tiles, N, p0, pw, k0,
+      hipLaunchKernelGGL(update_f64_kernel, grid, dim3(256), 0, s, (double *)tiles, N, p0, pw, k0,
                          K, mode, super_tile, G, G8, info);
     else
       hipLaunchKernelGGL(update_kernel<1>, grid, dim3(256), 0, s, (float *)tiles, N, p0, pw, k0,
