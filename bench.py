@@ -67,7 +67,10 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="fp64_n32768",
-                    choices=["fp64_n32768", "fp64_n1024", "fp64_n65536", "mixed_n65536"])
+                    choices=["fp64_n32768", "fp64_n1024", "fp64_n65536", "mixed_n65536", "serve"])
+    ap.add_argument("--duration", type=float, default=10.0, help="serve: seconds of arrivals")
+    ap.add_argument("--rate", type=float, default=200.0, help="serve: mean arrivals per second")
+    ap.add_argument("--workers", type=int, default=8, help="serve: concurrent requests")
     ap.add_argument("--n", type=int, default=0, help="override the order")
     ap.add_argument("--tile", type=int, default=128)
     ap.add_argument("--panel-width", type=int, default=0)
@@ -99,6 +102,8 @@ def main():
         P.set_option("super_tile", args.super_tile)
 
     wl = args.workload
+    if wl == "serve":
+        return bench_serve(args)
     n = args.n or {"fp64_n32768": 32768, "fp64_n1024": 1024, "fp64_n65536": 65536, "mixed_n65536": 65536}[wl]
     tile = args.tile
     steps, warmup = args.steps, args.warmup
@@ -241,6 +246,49 @@ def main():
     out.update(extra)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_n)
+    print(json.dumps(out), flush=True)
+
+
+def bench_serve(args):
+    """Poisson stream of GP solves replayed in real time against the server."""
+    import torch
+    import gp_inputs
+    from paper_2605_13209_amd.serve import HipExecutor, Server, SolveRequest
+    stream = gp_inputs.serving_stream(duration_s=args.duration, rate=args.rate, seed=0)
+
+    def to_req(r):
+        return SolveRequest(X=r.features(), B=r.rhs(), lengthscale=r.lengthscale, variance=1.0,
+                            noise=r.noise, key=r.key, rid=r.rid, tol=1e-10)
+
+    ex = HipExecutor(precision="fp32", method="ir", workers=args.workers)
+    with Server(ex, hbm_budget=200e9, max_inflight=args.workers) as srv:  # warm-up, not timed
+        for f in [srv.submit(to_req(r)) for r in gp_inputs.serving_stream(duration_s=0.1, seed=1)[:8]]:
+            f.result()
+    torch.cuda.synchronize()
+    pending = [to_req(r) for r in stream]  # host-side inputs prepared before the clock starts
+    srv = Server(ex, hbm_budget=200e9, max_inflight=args.workers)
+    futs = []
+    t0 = time.perf_counter()
+    for rq, r in zip(pending, stream):
+        delay = t0 + r.arrival - time.perf_counter()
+        if delay > 0:
+            time.sleep(delay)
+        rq.t_arrival = time.perf_counter()
+        futs.append(srv.submit(rq))
+    for f in futs:
+        f.result()
+    wall = time.perf_counter() - t0
+    st = srv.stats()
+    srv.close()
+    out = {"metric": METRIC, "value": round(st["gflops"], 2), "unit": "GFLOP/s", "n_gpus": 1,
+           "steps": len(futs), "warmup": 8, "ms_per_step": round(wall * 1e3 / max(1, len(futs)), 3),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64",
+           "data": "synthetic",
+           "config": {"workload": "serve_poisson", "rate_per_s": args.rate, "duration_s": args.duration,
+                      "n": "round(exp(U[ln 256, ln 8192]))", "rhs": "U{1..64}", "lengthscale": "U[0.3,2]",
+                      "noise": "U[0.01,1]", "repeat_keys": 0.25, "precision": "fp32 factor + FP64 IR",
+                      "hbm_budget_gb": 200, "workers": args.workers, "seed": 0},
+           "roofline": None, "serving": st, "wall_s": round(wall, 3)}
     print(json.dumps(out), flush=True)
 
 

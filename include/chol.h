@@ -19,8 +19,11 @@
  *   and return after enqueueing, unless stated otherwise.
  * - Ownership: the caller allocates and frees all device memory.  The library
  *   never allocates device memory; it owns only the small host handle
- *   returned by chol_factor, plus one side stream and a few events per device
- *   that it creates on first use and keeps until the process ends.
+ *   returned by chol_factor, plus one side stream and a few events per
+ *   (device, caller stream) pair, created on first use and kept until the
+ *   process ends.
+ * - Threads: calls on different streams may run concurrently from different
+ *   host threads; calls that share a stream must not overlap.
  * - Return value: CHOL_OK (0) on success; -i when argument i (1-based) is
  *   invalid; one of the negative CHOL_ERR_* codes otherwise.  Nothing is
  *   enqueued when an argument is rejected.
@@ -129,6 +132,25 @@ int chol_factor(const double *A, int64_t n, int64_t lda, int precision,
                 int tile, void *workspace, size_t ws_bytes, chol_handle *F,
                 int64_t *info, void *stream);
 
+/* ---- chol_factor_ex ----------------------------------------------------
+ * chol_factor with per-call schedule options instead of the process-wide
+ * ones (for concurrent callers such as the serving loop).  Any field <= 0
+ * (or lookahead < 0) falls back to the process-wide value; opts may be NULL.
+ * tile: 64 or 128 (0 = chol_tile_default); panel_width: 1..8; lookahead: 0/1;
+ * super_tile: 1..64.  The schedule never changes the computed factor.     */
+typedef struct {
+  int32_t tile;
+  int32_t panel_width;
+  int32_t lookahead;
+  int32_t super_tile;
+  int32_t graph; /* 1: capture / replay a HIP graph; 0: direct launches; <0: process-wide */
+} chol_factor_opts;
+
+int chol_factor_ex(const double *A, int64_t n, int64_t lda, int precision,
+                   const chol_factor_opts *opts, void *workspace,
+                   size_t ws_bytes, chol_handle *F, int64_t *info,
+                   void *stream);
+
 /* Synchronises the factor's stream and reports info (0 = success).       */
 int chol_get_info(chol_handle F, int64_t *info);
 
@@ -220,8 +242,12 @@ void chol_profile_reset(void);
  *                  trailing update on a second stream (default 1).
  * "super_tile"   : side, in tiles, of the groups the trailing-update grid
  *                  walks through together for cache reuse (default 8).
- * "graph"        : 1 replays a captured HIP graph of the factorisation for
- *                  repeated (n, tile, precision) calls (default 0).
+ * "graph"        : 1 captures the factorisation's launches (on the caller's
+ *                  stream and the side stream) into a HIP graph on the first
+ *                  call with a given (A, lda, n, precision, tile, schedule,
+ *                  workspace) and replays it on later identical calls; the
+ *                  32 most recent graphs per process are kept (default 0).
+ *                  Not used for CHOL_FP16_SCALED or while profiling.
  * "profile"      : 1 records kernel timing (see chol_profile_read).
  * Returns CHOL_OK or -1 (unknown key) / -2 (value out of range).         */
 int chol_set_option(const char *key, int64_t value);

@@ -34,6 +34,11 @@ class CholError(RuntimeError):
         super().__init__(f"{what}: status {status} ({chol_status_string(status)})")
 
 
+class FactorOpts(ctypes.Structure):
+    _fields_ = [("tile", ctypes.c_int32), ("panel_width", ctypes.c_int32), ("lookahead", ctypes.c_int32),
+                ("super_tile", ctypes.c_int32), ("graph", ctypes.c_int32)]
+
+
 class RefineReport(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("converged", ctypes.c_int32), ("cert", ctypes.c_double),
                 ("resid_norm", ctypes.c_double), ("time_ms", ctypes.c_double)]
@@ -46,6 +51,8 @@ EXPORTS = {
     "chol_tile_default": (_int, [_i64, _int]),
     "chol_factor": (_int, [_vp, _i64, _i64, _int, _int, _vp, _sz, ctypes.POINTER(_vp),
                            ctypes.POINTER(_i64), _vp]),
+    "chol_factor_ex": (_int, [_vp, _i64, _i64, _int, ctypes.POINTER(FactorOpts), _vp, _sz, ctypes.POINTER(_vp),
+                              ctypes.POINTER(_i64), _vp]),
     "chol_get_info": (_int, [_vp, ctypes.POINTER(_i64)]),
     "chol_solve": (_int, [_vp, _vp, _i64, _i64, _vp]),
     "chol_refine_bytes": (_sz, [_i64, _i64, _int]),
@@ -219,8 +226,11 @@ class Factor:
 
 
 def chol_factor(A: torch.Tensor, precision: str | int = "fp64", tile: int = 0, *,
-                workspace: torch.Tensor | None = None, sync: bool = True, stream=None) -> Factor:
-    """Factor A = L L^T on the GPU.  With sync=True, raises CholError(CHOL_ERR_NOT_SPD) if info > 0."""
+                workspace: torch.Tensor | None = None, sync: bool = True, stream=None,
+                panel_width: int = 0, lookahead: int = -1, super_tile: int = 0, graph: int = -1) -> Factor:
+    """Factor A = L L^T on the GPU (chol_factor_ex).  With sync=True, raises
+    CholError(CHOL_ERR_NOT_SPD) if info > 0.  panel_width / lookahead /
+    super_tile override the process-wide schedule options for this call."""
     _need_device(A, "A")
     n = A.shape[0]
     p = int(PRECISIONS.get(precision, precision))
@@ -232,9 +242,10 @@ def chol_factor(A: torch.Tensor, precision: str | int = "fp64", tile: int = 0, *
     h = _vp()
     info = _i64(0)
     st = _stream(stream)
-    rc = lib().chol_factor(A.data_ptr(), n, _ld(A), p, int(tile), workspace.data_ptr(),
-                           workspace.numel() * workspace.element_size(), ctypes.byref(h),
-                           ctypes.byref(info) if sync else None, st)
+    opts = FactorOpts(int(tile), int(panel_width), int(lookahead), int(super_tile), int(graph))
+    rc = lib().chol_factor_ex(A.data_ptr(), n, _ld(A), p, ctypes.byref(opts), workspace.data_ptr(),
+                              workspace.numel() * workspace.element_size(), ctypes.byref(h),
+                              ctypes.byref(info) if sync else None, st)
     _check(rc, "chol_factor")
     F = Factor(h, workspace, st)
     if sync and info.value != 0:

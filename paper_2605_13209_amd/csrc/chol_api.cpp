@@ -42,33 +42,70 @@ struct Options {
 };
 Options g_opt;
 
-// Per-device side stream and events (created on first use, never destroyed).
-struct DeviceCtx {
-  bool ready = false;
+// Lookahead resources: a side stream and four events per (device, caller
+// stream), created on first use and kept until the process ends, so that
+// factorisations issued concurrently on different caller streams (e.g. by
+// the serving loop's worker threads) never share them.
+struct SideCtx {
+  int device = -1;
+  hipStream_t caller = nullptr;
   hipStream_t side = nullptr;
   hipEvent_t ev_fork = nullptr, ev_panel = nullptr, ev_bulk = nullptr, ev_join = nullptr;
 };
 std::mutex g_ctx_mu;
-DeviceCtx g_ctx[64];
+std::vector<SideCtx *> g_ctx;
 
-int get_ctx(DeviceCtx **out) {
+int get_ctx(hipStream_t caller, SideCtx **out) {
   int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return CHOL_ERR_HIP;
+  if (hipGetDevice(&dev) != hipSuccess) return CHOL_ERR_HIP;
   std::lock_guard<std::mutex> lk(g_ctx_mu);
-  DeviceCtx &c = g_ctx[dev];
-  if (!c.ready) {
-    if (hipStreamCreateWithFlags(&c.side, hipStreamNonBlocking) != hipSuccess) return CHOL_ERR_HIP;
-    const unsigned fl = hipEventDisableTiming;
-    if (hipEventCreateWithFlags(&c.ev_fork, fl) != hipSuccess ||
-        hipEventCreateWithFlags(&c.ev_panel, fl) != hipSuccess ||
-        hipEventCreateWithFlags(&c.ev_bulk, fl) != hipSuccess ||
-        hipEventCreateWithFlags(&c.ev_join, fl) != hipSuccess)
-      return CHOL_ERR_HIP;
-    c.ready = true;
+  for (SideCtx *c : g_ctx)
+    if (c->device == dev && c->caller == caller) {
+      *out = c;
+      return CHOL_OK;
+    }
+  SideCtx *c = new SideCtx();
+  c->device = dev;
+  c->caller = caller;
+  if (hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess) {
+    delete c;
+    return CHOL_ERR_HIP;
   }
-  *out = &c;
+  const unsigned fl = hipEventDisableTiming;
+  if (hipEventCreateWithFlags(&c->ev_fork, fl) != hipSuccess ||
+      hipEventCreateWithFlags(&c->ev_panel, fl) != hipSuccess ||
+      hipEventCreateWithFlags(&c->ev_bulk, fl) != hipSuccess ||
+      hipEventCreateWithFlags(&c->ev_join, fl) != hipSuccess)
+    return CHOL_ERR_HIP;
+  g_ctx.push_back(c);
+  *out = c;
   return CHOL_OK;
 }
+
+// Captured factorisations (option "graph"): one executable graph per
+// (A, lda, n, precision, tile, schedule, workspace), replayed on later calls
+// with the same arguments.  Kernels take buffer addresses as arguments, so a
+// graph is only valid for the buffers it was captured with.
+struct GraphKey {
+  const void *A;
+  int64_t n, lda;
+  int precision, tile;
+  int64_t w;
+  int la, S;
+  void *ws;
+  bool operator==(const GraphKey &o) const {
+    return A == o.A && n == o.n && lda == o.lda && precision == o.precision && tile == o.tile &&
+           w == o.w && la == o.la && S == o.S && ws == o.ws;
+  }
+};
+struct GraphEntry {
+  GraphKey key;
+  int device;
+  hipGraphExec_t exec;
+};
+std::mutex g_graph_mu;
+std::vector<GraphEntry> g_graphs;  // most recently used last
+constexpr size_t kMaxGraphs = 32;
 
 // Event-bracketed timing of the trailing-update launches (option "profile").
 struct ProfRec {
@@ -271,64 +308,16 @@ static void factor_panel(chol_factor_s *F, int64_t c0, int64_t c1, int st, hipSt
   }
 }
 
-int chol_factor(const double *A, int64_t n, int64_t lda, int precision, int tile,
-                void *workspace, size_t ws_bytes, chol_handle *Fout, int64_t *info,
-                void *stream) {
-  if (n > 0 && !A) return -1;
-  if (n < 0) return -2;
-  if (lda < (n > 1 ? n : 1)) return -3;
-  if (precision < CHOL_FP64 || precision > CHOL_FP16_SCALED) return -4;
-  if (tile == 0) tile = chol_tile_default(n, precision);
-  if (!tile_ok(tile)) return -5;
-  if (!workspace || ((uintptr_t)workspace & 255)) return -6;
-  const size_t need = chol_factor_bytes(n, precision, tile);
-  if (ws_bytes < need) return CHOL_ERR_WORKSPACE;
-  if (!Fout) return -8;
-  if (precision == CHOL_FP16_SCALED && tile != 128) return CHOL_ERR_UNSUPPORTED;
-
-  DeviceCtx *ctx = nullptr;
-  int rc = get_ctx(&ctx);
-  if (rc) return rc;
-
-  chol_factor_s *F = new chol_factor_s();
-  F->n = n;
-  F->b = tile;
-  F->N = (n + tile - 1) / tile;
-  F->precision = precision;
-  (void)hipGetDevice(&F->device);
-  F->d_info = (int64_t *)workspace;
-  F->tiles = (char *)workspace + kHeader;
-  F->diag_t = (char *)F->tiles + (size_t)tile_count(F->N) * (size_t)tile * tile * esize_of(precision);
-  F->stream = (hipStream_t)stream;
-  const int st = store_of(precision);
-  const int64_t N = F->N;
+// Enqueue the whole factorisation (clear info, pack, column steps) on the
+// factor's stream and, with lookahead, the side stream joined back into it.
+static int enqueue_factor(chol_factor_s *F, SideCtx *ctx, const double *A, int64_t lda, int st,
+                          double pack_scale, int64_t w, int S, bool la) {
+  const int64_t N = F->N, n = F->n;
   const int b = F->b;
+  const int fp16 = F->precision == CHOL_FP16_SCALED;
   hipStream_t s = F->stream;
-
-  // Scaling for the FP16 form: the factor of H = A / s is computed, with s
-  // the largest diagonal entry (one read-back of the diagonal).
-  double pack_scale = 1.0;
-  if (precision == CHOL_FP16_SCALED && n > 0) {
-    std::vector<double> diag((size_t)n);
-    HIP_OK(hipStreamSynchronize(s));
-    HIP_OK(hipMemcpy2D(diag.data(), sizeof(double), A, (size_t)(lda + 1) * sizeof(double),
-                       sizeof(double), (size_t)n, hipMemcpyDeviceToHost));
-    double mx = 0.0;
-    for (double v : diag) mx = std::fmax(mx, v);
-    if (!(mx > 0.0)) mx = 1.0;
-    F->scale = mx;
-    pack_scale = 1.0 / mx;
-  }
-
   launch_clear_i64(F->d_info, 1, s);
   launch_pack(A, n, lda, F->tiles, st, b, N, pack_scale, s);
-
-  // panel width: tile columns per Step-3 pass over the far trailing matrix
-  const int64_t w = g_opt.panel_width > 0 ? (int64_t)g_opt.panel_width : (N >= 64 ? 4 : 2);
-  const int S = (int)g_opt.super_tile;
-  const int fp16 = precision == CHOL_FP16_SCALED;
-  const bool la = g_opt.lookahead != 0 && N > w;
-
   if (!la) {
     for (int64_t c0 = 0; c0 < N; c0 += w) {
       const int64_t c1 = std::min<int64_t>(c0 + w, N);
@@ -361,6 +350,141 @@ int chol_factor(const double *A, int64_t n, int64_t lda, int precision, int tile
     }
     HIP_OK(hipEventRecord(ctx->ev_join, p));
     HIP_OK(hipStreamWaitEvent(s, ctx->ev_join, 0));
+  }
+  return hipGetLastError() == hipSuccess ? CHOL_OK : CHOL_ERR_HIP;
+}
+
+int chol_factor(const double *A, int64_t n, int64_t lda, int precision, int tile,
+                void *workspace, size_t ws_bytes, chol_handle *Fout, int64_t *info,
+                void *stream) {
+  chol_factor_opts o{tile, 0, -1, 0, -1};
+  return chol_factor_ex(A, n, lda, precision, &o, workspace, ws_bytes, Fout, info, stream);
+}
+
+int chol_factor_ex(const double *A, int64_t n, int64_t lda, int precision,
+                   const chol_factor_opts *opts, void *workspace, size_t ws_bytes,
+                   chol_handle *Fout, int64_t *info, void *stream) {
+  int tile = opts ? opts->tile : 0;
+  if (opts && (opts->panel_width > 8 || opts->super_tile > 64 || opts->lookahead > 1)) return -5;
+  if (n > 0 && !A) return -1;
+  if (n < 0) return -2;
+  if (lda < (n > 1 ? n : 1)) return -3;
+  if (precision < CHOL_FP64 || precision > CHOL_FP16_SCALED) return -4;
+  if (tile == 0) tile = chol_tile_default(n, precision);
+  if (!tile_ok(tile)) return -5;
+  if (!workspace || ((uintptr_t)workspace & 255)) return -6;
+  const size_t need = chol_factor_bytes(n, precision, tile);
+  if (ws_bytes < need) return CHOL_ERR_WORKSPACE;
+  if (!Fout) return -8;
+  if (precision == CHOL_FP16_SCALED && tile != 128) return CHOL_ERR_UNSUPPORTED;
+
+  SideCtx *ctx = nullptr;
+  int rc = get_ctx((hipStream_t)stream, &ctx);
+  if (rc) return rc;
+
+  chol_factor_s *F = new chol_factor_s();
+  F->n = n;
+  F->b = tile;
+  F->N = (n + tile - 1) / tile;
+  F->precision = precision;
+  (void)hipGetDevice(&F->device);
+  F->d_info = (int64_t *)workspace;
+  F->tiles = (char *)workspace + kHeader;
+  F->diag_t = (char *)F->tiles + (size_t)tile_count(F->N) * (size_t)tile * tile * esize_of(precision);
+  F->stream = (hipStream_t)stream;
+  const int st = store_of(precision);
+  const int64_t N = F->N;
+  const int b = F->b;
+  hipStream_t s = F->stream;
+
+  // Scaling for the FP16 form: the factor of H = A / s is computed, with s
+  // the largest diagonal entry (one read-back of the diagonal).
+  double pack_scale = 1.0;
+  if (precision == CHOL_FP16_SCALED && n > 0) {
+    std::vector<double> diag((size_t)n);
+    HIP_OK(hipStreamSynchronize(s));
+    HIP_OK(hipMemcpy2D(diag.data(), sizeof(double), A, (size_t)(lda + 1) * sizeof(double),
+                       sizeof(double), (size_t)n, hipMemcpyDeviceToHost));
+    double mx = 0.0;
+    for (double v : diag) mx = std::fmax(mx, v);
+    if (!(mx > 0.0)) mx = 1.0;
+    F->scale = mx;
+    pack_scale = 1.0 / mx;
+  }
+
+  // panel width: tile columns per Step-3 pass over the far trailing matrix
+  const int64_t pw_opt =
+      (opts && opts->panel_width > 0) ? (int64_t)opts->panel_width : g_opt.panel_width.load();
+  const int64_t w = pw_opt > 0 ? pw_opt : (N >= 64 ? 4 : 2);
+  const int S =
+      (int)((opts && opts->super_tile > 0) ? (int64_t)opts->super_tile : g_opt.super_tile.load());
+  const int fp16 = precision == CHOL_FP16_SCALED;
+  const int64_t la_opt =
+      (opts && opts->lookahead >= 0) ? (int64_t)opts->lookahead : g_opt.lookahead.load();
+  const bool la = la_opt != 0 && N > w;
+
+
+  // Stream capture is not allowed on the legacy NULL stream: direct launches there.
+  const bool graph = (opts && opts->graph >= 0 ? opts->graph != 0 : g_opt.graph != 0) &&
+                     precision != CHOL_FP16_SCALED && !g_opt.profile && s != nullptr;
+  GraphKey gk{A, n, lda, precision, tile, w, la ? 1 : 0, S, workspace};
+  if (graph) {
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    std::lock_guard<std::mutex> lk(g_graph_mu);
+    for (size_t e = 0; e < g_graphs.size(); ++e) {
+      if (g_graphs[e].device == dev && g_graphs[e].key == gk) {
+        GraphEntry ge = g_graphs[e];
+        g_graphs.erase(g_graphs.begin() + e);
+        g_graphs.push_back(ge);
+        if (hipGraphLaunch(ge.exec, s) != hipSuccess) {
+          delete F;
+          return CHOL_ERR_HIP;
+        }
+        *Fout = F;
+        if (info) return chol_get_info(F, info);
+        return CHOL_OK;
+      }
+    }
+    if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+      delete F;
+      return CHOL_ERR_HIP;
+    }
+  }
+  rc = enqueue_factor(F, ctx, A, lda, st, pack_scale, w, S, la);
+  if (rc != CHOL_OK) {
+    if (graph) {
+      hipGraph_t g = nullptr;
+      (void)hipStreamEndCapture(s, &g);
+      if (g) (void)hipGraphDestroy(g);
+    }
+    delete F;
+    return rc;
+  }
+  if (graph) {
+    hipGraph_t g = nullptr;
+    hipGraphExec_t ge = nullptr;
+    if (hipStreamEndCapture(s, &g) != hipSuccess ||
+        hipGraphInstantiate(&ge, g, nullptr, nullptr, 0) != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      delete F;
+      return CHOL_ERR_HIP;
+    }
+    (void)hipGraphDestroy(g);
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    {
+      std::lock_guard<std::mutex> lk(g_graph_mu);
+      if (g_graphs.size() >= kMaxGraphs) {
+        (void)hipGraphExecDestroy(g_graphs.front().exec);
+        g_graphs.erase(g_graphs.begin());
+      }
+      g_graphs.push_back({gk, dev, ge});
+    }
+    if (hipGraphLaunch(ge, s) != hipSuccess) {
+      delete F;
+      return CHOL_ERR_HIP;
+    }
   }
   if (hipGetLastError() != hipSuccess) {
     delete F;

@@ -20,7 +20,7 @@ namespace {
 // one column k per step:
 //   (1) the owner of (k, k) publishes the pivot;            barrier
 //   (2) everyone checks it (uniform exit on failure); the owners of column k
-//       divide it by sqrt(pivot) and publish it;           barrier
+//       scale it by 1/sqrt(pivot) and publish it;          barrier
 //   (3) every thread applies the rank-1 update to its trailing elements.
 // Register indices are compile-time: the column loop is split into an
 // unrolled block index km and a runtime offset kr (k = 16 km + kr), and the
@@ -64,12 +64,13 @@ __global__ __launch_bounds__(256) void potrf_kernel(T *__restrict__ tiles, int64
         return;
       }
       const double lkk = sqrt(d);
+      const double rl = 1.0 / lkk;  // the column is scaled by the reciprocal
       if (tc == kr) {
 #pragma unroll
         for (int m = km; m < M; ++m) {
           const int i = tr + 16 * m;
           if (i > k) {
-            a[m][km] = a[m][km] / lkk;
+            a[m][km] = a[m][km] * rl;
             col[i] = a[m][km];
           } else if (i == k) {
             a[m][km] = lkk;
@@ -116,31 +117,41 @@ __global__ __launch_bounds__(256) void potrf_kernel(T *__restrict__ tiles, int64
 // threads per tile; thread (r, h) handles row r (r = t mod B) and owns the
 // column blocks q (16 columns each) with q mod H = h (H = 256 / B), keeping
 // its solved values in registers.  For block q:
-//   the 16-row strip of L needed (rows 16q.., columns < 16q + 16) is staged
-//   in LDS and read as broadcasts;
+//   the 16-row strip of L needed (rows 16q.., columns < 16q + 16) sits in
+//   LDS and is read as broadcasts; the strip of block q+1 is loaded into
+//   registers while block q computes (double-buffered strips);
 //   every thread sums x_m L[16q+u][m] over its own earlier blocks;
 //   the owner of block q adds the H partial sums (in a fixed order) to the
-//   right-hand side and solves the 16 x 16 triangle by substitution.
+//   right-hand side and solves the 16 x 16 triangle by substitution,
+//   multiplying by reciprocals of the diagonal.
 template <int B, typename T>
 __global__ __launch_bounds__(256) void trsm_kernel(T *__restrict__ tiles, int64_t N, int64_t c,
                                                    const int64_t *__restrict__ info) {
   if (*info != 0) return;
   constexpr int CB = 16, NB = B / CB, H = 256 / B;
-  __shared__ double ls[B * CB];            // ls[m * CB + u] = L[16q + u][m]
+  __shared__ double ls[2][B * CB];         // ls[.][m * CB + u] = L[16q + u][m]
   __shared__ double part[H][CB][B + 1];    // partial sums per (h, u, row)
   const int64_t i = c + 1 + blockIdx.x;
   const T *L = tiles + tile_index(c, c, N) * (int64_t)(B * B);
   T *X = tiles + tile_index(i, c, N) * (int64_t)(B * B);
   const int t = threadIdx.x, r = t % B, h = t / B;
+  // strip q: elements e < (q + 1) * CB * CB, e = m * CB + u -> L[m * B + 16q + u]
+  for (int e = t; e < CB * CB; e += 256) ls[0][e] = (double)L[(e / CB) * B + (e % CB)];
+  __syncthreads();
   double x[NB / H][CB];
 #pragma unroll
   for (int q = 0; q < NB; ++q) {
-    __syncthreads();
-    for (int e = t; e < (q + 1) * CB * CB; e += 256) {
-      const int m = e / CB, u = e % CB;
-      ls[m * CB + u] = (double)L[m * B + q * CB + u];
+    const double *lq = ls[q & 1];
+    // prefetch the next strip into registers
+    constexpr int MAXP = (NB + 1) * CB * CB / 256 + 1;
+    double nxt[MAXP];
+    if (q + 1 < NB) {
+#pragma unroll
+      for (int x2 = 0; x2 < MAXP; ++x2) {
+        const int e = t + 256 * x2;
+        if (e < (q + 2) * CB * CB) nxt[x2] = (double)L[(e / CB) * B + (q + 1) * CB + (e % CB)];
+      }
     }
-    __syncthreads();
     double acc[CB];
 #pragma unroll
     for (int u = 0; u < CB; ++u) acc[u] = 0.0;
@@ -151,7 +162,7 @@ __global__ __launch_bounds__(256) void trsm_kernel(T *__restrict__ tiles, int64_
         for (int mm = 0; mm < CB; ++mm) {
           const double xm = x[qq / H][mm];
 #pragma unroll
-          for (int u = 0; u < CB; ++u) acc[u] += xm * ls[(qq * CB + mm) * CB + u];
+          for (int u = 0; u < CB; ++u) acc[u] += xm * lq[(qq * CB + mm) * CB + u];
         }
       }
     }
@@ -159,9 +170,10 @@ __global__ __launch_bounds__(256) void trsm_kernel(T *__restrict__ tiles, int64_
     for (int u = 0; u < CB; ++u) part[h][u][r] = acc[u];
     __syncthreads();
     if (h == q % H) {
-      double v[CB];
+      double v[CB], rd[CB];
 #pragma unroll
       for (int u = 0; u < CB; ++u) {
+        rd[u] = 1.0 / lq[(q * CB + u) * CB + u];
         double s = part[0][u][r];
 #pragma unroll
         for (int hh = 1; hh < H; ++hh) s += part[hh][u][r];
@@ -170,12 +182,20 @@ __global__ __launch_bounds__(256) void trsm_kernel(T *__restrict__ tiles, int64_
 #pragma unroll
       for (int u = 0; u < CB; ++u) {
 #pragma unroll
-        for (int w = 0; w < u; ++w) v[u] -= v[w] * ls[(q * CB + w) * CB + u];
-        v[u] = v[u] / ls[(q * CB + u) * CB + u];
+        for (int w = 0; w < u; ++w) v[u] -= v[w] * lq[(q * CB + w) * CB + u];
+        v[u] = v[u] * rd[u];
         x[q / H][u] = v[u];
         X[(q * CB + u) * B + r] = (T)v[u];
       }
     }
+    if (q + 1 < NB) {
+#pragma unroll
+      for (int x2 = 0; x2 < MAXP; ++x2) {
+        const int e = t + 256 * x2;
+        if (e < (q + 2) * CB * CB) ls[(q + 1) & 1][e] = nxt[x2];
+      }
+    }
+    __syncthreads();
   }
 }
 

@@ -268,3 +268,76 @@ def test_workspace_too_small_rejected():
     with pytest.raises(P.CholError) as e:
         P.chol_factor(A, "fp64", 64, workspace=ws)
     assert e.value.status == -101
+
+
+# ------------------------------------------------- scaled FP16 + refinement ---
+
+def test_fp16_scaled_factor_and_refine():
+    """FP16 operands / FP32 accumulation on H = A / s; refined to 1e-10 (well-conditioned GP)."""
+    n, k = 1000, 2
+    X, B = gp_inputs.gp_problem(n, seed=3, k=k)
+    hp = (0.5, 1.0, 1.0)
+    A = oracle.gp_assemble(X, *hp)
+    Lref, _ = oracle.cholesky(A)
+    xref, _, _, failed = oracle.refine(Lref, A, B, lam=hp[2], tol=1e-13)
+    assert failed == 0
+    Xd = torch.from_numpy(X).cuda()
+    Ad = P.gp_assemble(Xd, *hp)
+    F = P.chol_factor(Ad, "fp16_scaled", 128)
+    L = host(P.chol_factor_to_dense(F))
+    be = oracle.backward_error(A, L)
+    assert be <= 5e-3, be  # of order u_16 = 4.9e-4 times modest growth
+    for method in ("ir", "pcg"):
+        res = P.chol_refine_solve(F, dev(B), A=Ad, noise=hp[2], tol=1e-10, method=method, max_iter=60)
+        assert res.converged, (method, res.iters, res.cert)
+        x = host(res.X)
+        for c in range(k):
+            err = np.linalg.norm(x[:, c] - xref[:, c]) / np.linalg.norm(xref[:, c])
+            assert err <= 1e-10, (method, c, err)
+
+
+def test_fp16_scaled_solve_scaling():
+    """chol_solve with the scaled factor returns A^-1 b (not H^-1 b)."""
+    n = 600
+    X, B = gp_inputs.gp_problem(n, seed=4, k=1)
+    hp = (0.5, 2.0, 1.0)  # diagonal 3: a non-trivial scale
+    A = oracle.gp_assemble(X, *hp)
+    xnp = np.linalg.solve(A, B)
+    F = P.chol_factor(dev(A), "fp16_scaled", 128)
+    Bd = dev(B)
+    P.chol_solve(F, Bd)
+    err = np.linalg.norm(host(Bd) - xnp) / np.linalg.norm(xnp)
+    assert err <= 5e-2, err
+
+
+# ------------------------------------------------------------ HIP graphs ---
+
+@pytest.mark.parametrize("n", [1024, 1300])
+def test_graph_replay_bitwise(n):
+    """Captured factorisation replayed several times, with eager work and
+    synchronisations in between; every replay equals the eager factor, and a
+    replay after A changed equals the eager factor of the new A."""
+    X, _ = gp_inputs.gp_problem(n, seed=11)
+    A = dev(oracle.gp_assemble(X, 1.0, 1.0, 0.1))
+    s = torch.cuda.Stream()
+    need = P.chol_factor_bytes(n, "fp64", 128)
+    ws_g = torch.empty(need, dtype=torch.uint8, device="cuda")
+    ws_e = torch.empty(need, dtype=torch.uint8, device="cuda")
+    with torch.cuda.stream(s):
+        L_eager = host(P.chol_factor_to_dense(P.chol_factor(A, "fp64", 128, workspace=ws_e, graph=0, stream=s),
+                                              stream=s))
+        for rep in range(4):
+            F = P.chol_factor(A, "fp64", 128, workspace=ws_g, graph=1, stream=s)
+            assert F.info() == 0
+            L = host(P.chol_factor_to_dense(F, stream=s))
+            assert np.array_equal(L, L_eager), rep
+            # eager work between replays
+            P.chol_factor(A, "fp64", 128, workspace=ws_e, graph=0, stream=s)
+            torch.cuda.synchronize()
+        A2 = dev(oracle.gp_assemble(X, 0.7, 1.0, 0.2))
+        A.copy_(A2)
+        torch.cuda.synchronize()
+        L2_eager = host(P.chol_factor_to_dense(P.chol_factor(A, "fp64", 128, workspace=ws_e, graph=0,
+                                                             stream=s), stream=s))
+        F = P.chol_factor(A, "fp64", 128, workspace=ws_g, graph=1, stream=s)
+        assert np.array_equal(host(P.chol_factor_to_dense(F, stream=s)), L2_eager)
