@@ -15,9 +15,12 @@ Other workloads (``--workload``) print the same kind of JSON line:
                 solution of one right-hand side;
   fp64_n65536   the FP64 factorisation at n = 65536.
 
-The roofline object is measured live: every trailing-update launch (the
-dominant kernel) is bracketed by HIP events on the stream it runs on, and
-its algorithmic flop count is summed (chol_profile_read).  cpu_baseline
+The roofline object is measured live: every launch of the bulk
+trailing-triangle update (the dominant kernel, update_f64_kernel<0> or
+update_f32_kernel<0>) is bracketed by HIP events on the stream it runs on,
+and its algorithmic flop count is summed (chol_profile_read with profile
+mode 2).  The smaller panel-band launches of the same update, which run on
+the lookahead stream concurrently with it, are not part of the figure.  cpu_baseline
 times the CPU oracle (assembly + Cholesky + solve) on a bounded sample.
 """
 from __future__ import annotations
@@ -146,7 +149,7 @@ def main():
             raise RuntimeError(f"factorisation failed, info={F.info()}")
         P.chol_profile_reset()
         if not args.no_profile:
-            P.set_option("profile", 1)
+            P.set_option("profile", 2)
         t_step, t_asm, t_fac, t_s1, t_s16 = [], [], [], [], []
         torch.cuda.synchronize()
         wall0 = time.perf_counter()
@@ -198,15 +201,17 @@ def main():
                 torch.cuda.synchronize()
                 if rep == warmup and not args.no_profile and prec == "fp32" and method == "ir":
                     P.chol_profile_reset()
-                    P.set_option("profile", 1)
+                    P.set_option("profile", 2)
                 t0 = time.perf_counter()
                 F = P.chol_factor(A, prec, tile, workspace=ws, sync=False)
+                torch.cuda.synchronize()
+                tm = time.perf_counter()
                 r = P.chol_refine_solve(F, B1_src, A=A, noise=HP[2], tol=1e-10, method=method, out=b)
                 torch.cuda.synchronize()
                 t1 = time.perf_counter()
                 if rep >= warmup:
                     ts.append((t1 - t0) * 1e3)
-                    tf.append((t1 - t0) * 1e3 - r.time_ms)
+                    tf.append((tm - t0) * 1e3)
                     it.append(r.iters)
                     ce.append(r.cert)
                 del F
@@ -221,7 +226,7 @@ def main():
         flops = n ** 3 / 3
         best_mixed = min(res["fp32_ir"]["time_to_solution_ms"], res["fp32_pcg"]["time_to_solution_ms"])
         ms_step = best_mixed
-        value = flops / (res["fp32_ir"]["factor_ms"] * 1e-3) / 1e9
+        value = flops / (best_mixed * 1e-3) / 1e9  # n^3/3 over the whole time to a certified solution
         extra.update({"solutions": res,
                       "speedup_mixed_vs_fp64": round(res["fp64_ir"]["time_to_solution_ms"] / best_mixed, 3)})
         dtype = "f32"
@@ -235,7 +240,8 @@ def main():
         ach = kfl / (kms * 1e-3) / 1e12
         roofline = {"bound": "mfma", "achieved": round(ach, 3), "peak": peak, "unit": "TFLOP/s",
                     "frac": round(ach / peak, 4), "traffic": None,
-                    "kernel": "update_kernel (Step-3 trailing update)", "launches": kl,
+                    "kernel": ("update_f64_kernel<0>" if dtype == "f64" else "update_f32_kernel<0>")
+                    + " (Step-3 update of the trailing triangle)", "launches": kl,
                     "avg_launch_us": round(kms * 1e3 / kl, 2),
                     "avg_launch_gflop": round(kfl / kl / 1e9, 4)}
 

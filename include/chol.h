@@ -225,7 +225,9 @@ const char *chol_status_string(int status);
 /* ---- kernel timing ------------------------------------------------------
  * With option "profile" = 1, every launch of the Step-3 trailing-update
  * kernel is bracketed by a pair of HIP events recorded on the stream it is
- * launched on, and the launch's algorithmic flop count is accumulated
+ * launched on (with "profile" = 2 only the launches over a whole trailing
+ * triangle, not the panel-band ones), and the launch's algorithmic flop
+ * count is accumulated
  * (2 b^2 K per off-diagonal tile and b (b + 1) K per diagonal tile, K the
  * inner dimension of the launch).  chol_profile_read waits for the recorded
  * events and returns the summed kernel time (ms), the number of launches and
@@ -248,7 +250,12 @@ void chol_profile_reset(void);
  *                  workspace) and replays it on later identical calls; the
  *                  32 most recent graphs per process are kept (default 0).
  *                  Not used for CHOL_FP16_SCALED or while profiling.
- * "profile"      : 1 records kernel timing (see chol_profile_read).
+ * "profile"      : 1 records kernel timing, 2 only of the triangle launches
+ *                  (see chol_profile_read).
+ * "bulk_wg_cap"  : with lookahead, the far trailing update runs with at most
+ *                  this many (persistent) workgroups, leaving slots for the
+ *                  next panel's kernels (default 0 = no cap: one workgroup
+ *                  per tile measured fastest on MI355X).
  * Returns CHOL_OK or -1 (unknown key) / -2 (value out of range).         */
 int chol_set_option(const char *key, int64_t value);
 int64_t chol_get_option(const char *key);

@@ -39,6 +39,7 @@ struct Options {
   std::atomic<int64_t> super_tile{8};
   std::atomic<int64_t> graph{0};
   std::atomic<int64_t> profile{0};
+  std::atomic<int64_t> bulk_wg_cap{0};  // workgroups of the bulk update under lookahead (0 = all)
 };
 Options g_opt;
 
@@ -147,16 +148,17 @@ double update_flops(int b, int64_t N, int pw, int64_t k0, int64_t k1, int mode) 
 
 // launch_update, bracketed by events when profiling.
 void update(void *tiles, int st, int b, int64_t N, int64_t p0, int pw, int64_t k0, int64_t k1,
-            int mode, int S, int fp16, const int64_t *info, hipStream_t s) {
+            int mode, int S, int fp16, const int64_t *info, hipStream_t s, int64_t max_wg = 0) {
   if (N - k0 <= 0 || (mode == 1 && k1 <= k0)) return;
-  if (!g_opt.profile) {
-    launch_update(tiles, st, b, N, p0, pw, k0, k1, mode, S, fp16, info, s);
+  const int64_t prof = g_opt.profile;
+  if (!prof || (prof == 2 && mode != 0)) {
+    launch_update(tiles, st, b, N, p0, pw, k0, k1, mode, S, fp16, info, s, max_wg);
     return;
   }
   std::lock_guard<std::mutex> lk(g_prof_mu);
   hipEvent_t a = prof_event(), e = prof_event();
   if (a) (void)hipEventRecord(a, s);
-  launch_update(tiles, st, b, N, p0, pw, k0, k1, mode, S, fp16, info, s);
+  launch_update(tiles, st, b, N, p0, pw, k0, k1, mode, S, fp16, info, s, max_wg);
   if (e) (void)hipEventRecord(e, s);
   if (a && e) g_prof.push_back({a, e, update_flops(b, N, pw, k0, k1, mode)});
 }
@@ -215,8 +217,11 @@ int chol_set_option(const char *key, int64_t value) {
     if (value < 0 || value > 1) return -2;
     g_opt.graph = value;
   } else if (!strcmp(key, "profile")) {
-    if (value < 0 || value > 1) return -2;
+    if (value < 0 || value > 2) return -2;
     g_opt.profile = value;
+  } else if (!strcmp(key, "bulk_wg_cap")) {
+    if (value < 0 || value > (int64_t)1 << 30) return -2;
+    g_opt.bulk_wg_cap = value;
   } else {
     return -1;
   }
@@ -230,6 +235,7 @@ int64_t chol_get_option(const char *key) {
   if (!strcmp(key, "super_tile")) return g_opt.super_tile;
   if (!strcmp(key, "graph")) return g_opt.graph;
   if (!strcmp(key, "profile")) return g_opt.profile;
+  if (!strcmp(key, "bulk_wg_cap")) return g_opt.bulk_wg_cap;
   return -1;
 }
 
@@ -341,10 +347,13 @@ static int enqueue_factor(chol_factor_s *F, SideCtx *ctx, const double *A, int64
         update(F->tiles, st, b, N, c0, (int)(c1 - c0), c1, n1, /*band*/ 1, 8, fp16, F->d_info, p);
         factor_panel(F, c1, n1, st, p);
       }
-      // bulk update of the columns right of the next panel, on the main stream
+      // bulk update of the columns right of the next panel, on the main
+      // stream; while a next panel exists its workgroups are capped so that
+      // the side stream's kernels find free slots.
       HIP_OK(hipStreamWaitEvent(s, ctx->ev_panel, 0));
       if (n1 < N) {
-        update(F->tiles, st, b, N, c0, (int)(c1 - c0), n1, N, /*tri*/ 0, S, fp16, F->d_info, s);
+        update(F->tiles, st, b, N, c0, (int)(c1 - c0), n1, N, /*tri*/ 0, S, fp16, F->d_info, s,
+               g_opt.bulk_wg_cap.load());
       }
       HIP_OK(hipEventRecord(ctx->ev_bulk, s));
     }

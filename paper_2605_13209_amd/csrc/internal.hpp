@@ -59,9 +59,11 @@ void launch_trsm(void *tiles, int store, int b, int64_t N, int64_t c, const int6
 //   mode 0 (triangle): k0 <= k <= i < N;
 //   mode 1 (band)    : k in [k0, k1), k <= i < N  (k1 - k0 <= super_tile).
 // fp16 = 1 rounds the panel operands to FP16 (FP32 storage only).
+// max_wg > 0 caps the number of workgroups (each then walks several tiles),
+// leaving workgroup slots free for kernels on other streams.
 void launch_update(void *tiles, int store, int b, int64_t N, int64_t p0, int pw, int64_t k0,
                    int64_t k1, int mode, int super_tile, int fp16, const int64_t *info,
-                   hipStream_t s);
+                   hipStream_t s, int64_t max_wg = 0);
 
 // Triangular solves, in place on B (n x nrhs, ldb), FP64 arithmetic.  The
 // back substitution reads the transposed diagonal blocks from diag_t.

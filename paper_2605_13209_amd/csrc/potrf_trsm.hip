@@ -25,8 +25,9 @@ namespace {
 // Register indices are compile-time: the column loop is split into an
 // unrolled block index km and a runtime offset kr (k = 16 km + kr), and the
 // blocks that are inactive at block km are skipped at compile time.  The tile
-// is moved between HBM and registers through LDS so that the global accesses
-// are contiguous columns.  The kernel also stores L_cc^T (column-major) in a
+// is moved between HBM and registers through LDS, half a tile at a time (so
+// the kernel's LDS fits next to a trailing-update workgroup on one CU), with
+// contiguous global accesses.  The kernel also stores L_cc^T (column-major) in a
 // side array, so that the back substitution reads the diagonal blocks along
 // columns as well.
 template <int B, typename T>
@@ -36,21 +37,27 @@ __global__ __launch_bounds__(256) void potrf_kernel(T *__restrict__ tiles, int64
   if (*info != 0) return;
   constexpr int M = B / 16;
   constexpr int LD = B + 1;
-  __shared__ double stage[B * LD];
+  constexpr int HC = B / 2;  // columns staged per half
+  __shared__ double stage[HC * LD];
   __shared__ double col[B];
   __shared__ double piv;
   T *tile = tiles + tile_index(c, c, N) * (int64_t)(B * B);
   const int t = threadIdx.x, tc = t & 15, tr = t >> 4;
-  for (int e = t; e < B * B; e += 256) {
-    const int r = e % B, cc = e / B;
-    stage[cc * LD + r] = (double)tile[e];
-  }
-  __syncthreads();
   double a[M][M];
 #pragma unroll
-  for (int m = 0; m < M; ++m)
+  for (int hf = 0; hf < 2; ++hf) {
+    for (int e = t; e < HC * B; e += 256) {
+      const int r = e % B, cc = e / B;
+      stage[cc * LD + r] = (double)tile[(hf * HC + cc) * B + r];
+    }
+    __syncthreads();
 #pragma unroll
-    for (int n = 0; n < M; ++n) a[m][n] = stage[(tc + 16 * n) * LD + tr + 16 * m];
+    for (int m = 0; m < M; ++m)
+#pragma unroll
+      for (int n = hf * M / 2; n < (hf + 1) * M / 2; ++n)
+        a[m][n] = stage[(tc + 16 * n - hf * HC) * LD + tr + 16 * m];
+    __syncthreads();
+  }
 
 #pragma unroll
   for (int km = 0; km < M; ++km) {
@@ -94,20 +101,27 @@ __global__ __launch_bounds__(256) void potrf_kernel(T *__restrict__ tiles, int64
       }
     }
   }
-  __syncthreads();
-#pragma unroll
-  for (int m = 0; m < M; ++m)
-#pragma unroll
-    for (int n = 0; n < M; ++n) {
-      const int i = tr + 16 * m, j = tc + 16 * n;
-      stage[j * LD + i] = (i >= j) ? a[m][n] : 0.0;
-    }
-  __syncthreads();
   T *tt = diag_t + c * (int64_t)(B * B);  // L_cc^T, used by the back substitution
-  for (int e = t; e < B * B; e += 256) {
-    const int r = e % B, cc = e / B;
-    tile[e] = (T)stage[cc * LD + r];
-    tt[e] = (T)stage[r * LD + cc];
+#pragma unroll
+  for (int hf = 0; hf < 2; ++hf) {
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < M; ++m)
+#pragma unroll
+      for (int n = hf * M / 2; n < (hf + 1) * M / 2; ++n) {
+        const int i = tr + 16 * m, j = tc + 16 * n;
+        stage[(j - hf * HC) * LD + i] = (i >= j) ? a[m][n] : 0.0;
+      }
+    __syncthreads();
+    // columns hf*HC.. of L, and the same rows of L^T
+    for (int e = t; e < HC * B; e += 256) {
+      const int r = e % B, cc = e / B;
+      tile[(hf * HC + cc) * B + r] = (T)stage[cc * LD + r];
+    }
+    for (int e = t; e < HC * B; e += 256) {
+      const int cc = e % HC, r = e / HC;  // L^T(r', c') = L(c', r'): row r of L^T, column hf*HC+cc
+      tt[(hf * HC + cc) + (int64_t)r * B] = (T)stage[cc * LD + r];
+    }
   }
 }
 

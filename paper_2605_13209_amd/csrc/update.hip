@@ -9,210 +9,167 @@
 // gfx950 design
 // -------------
 // * One workgroup (4 waves, 2 x 2) per 128 x 128 output tile; each wave owns
-//   a 64 x 64 block as 4 x 4 MFMA 16x16 blocks (FP64: v_mfma_f64_16x16x4,
-//   FP32: v_mfma_f32_16x16x4; FP16 operands: v_mfma_f32_16x16x32_f16).
-//   The accumulators are initialised with the C tile itself and the panel
-//   operand A is negated when staged, so each MFMA performs C -= a b^T.
-// * Rows are interleaved across the 4 MFMA blocks of a wave so that a lane's
-//   four A (or B) fragments come from one or two 16-byte LDS reads that are
-//   contiguous across lanes (conflict-free), and a lane's accumulators form
-//   16-byte runs of C columns (vector loads/stores of C straight to and from
-//   HBM).  See the row-interleave comment in update_kernel.
-// * The panel is streamed through LDS in chunks of KC columns (128 bytes per
-//   tile row), double-buffered; global loads of chunk s+1 are in flight while
-//   chunk s is multiplied.  LDS rows are padded to avoid bank conflicts.
+//   a 64 x 64 block (FP64: v_mfma_f64_4x4x4_4b_f64, FP32:
+//   v_mfma_f32_16x16x4_f32, FP16 operands: v_mfma_f32_16x16x32_f16).
+//   The accumulators start at -C and the tile is negated back on store, so
+//   the panel operands are used unmodified and each MFMA adds a b^T.
+// * Rows are interleaved across the MFMA blocks of a wave so that a lane's
+//   A (or B) fragments come from 16-byte LDS reads that are contiguous
+//   across lanes, and a lane's accumulators form 16-byte runs of C columns
+//   (vector loads/stores of C straight to and from HBM).
+// * FP64 / FP32: the panel is streamed through LDS in chunks of 128 bytes per
+//   tile row by LDS DMA (global_load_lds_dwordx4), two chunks ahead, and the
+//   fragments of the next k-step are read while the MFMAs of the current one
+//   run; one barrier per chunk.  FP16 operands are rounded when staged.
 // * Work mapping: the tile region is walked in super-tiles of S x S tiles
 //   and the linear order is split into 8 contiguous ranges, one per XCD
 //   (workgroup w runs on XCD w mod 8), so the workgroups that share an L2
-//   also share panel rows.
+//   also share panel rows.  Workgroups are persistent: a grid smaller than
+//   the tile count walks the range.
 #include "internal.hpp"
 #include "tile_map.hpp"
 
 namespace chol {
 namespace {
 
-typedef double v4d __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 typedef _Float16 v8h __attribute__((ext_vector_type(8)));
 
-constexpr int BT = 128;  // tile side handled by this kernel
+constexpr int BT = 128;  // tile side handled by the matrix-core kernels
 
-// Storage element type, MFMA accumulator type and chunk depth per mode.
-template <int MODE> struct Cfg;
-// MODE 0: FP64 storage and arithmetic.
-template <> struct Cfg<0> {
-  using T = double;
-  using acc_t = v4d;
-  static constexpr int KC = 16;   // columns per LDS chunk (16 * 8 B = 128 B)
-  static constexpr int PAD = 4;   // LDS row padding (elements)
-};
-// MODE 1: FP32 storage and arithmetic.
-template <> struct Cfg<1> {
-  using T = float;
-  using acc_t = v4f;
-  static constexpr int KC = 32;
-  static constexpr int PAD = 8;
-};
-
-__device__ inline uint4 neg_f64x2(uint4 v) {
-  v.y ^= 0x80000000u;
-  v.w ^= 0x80000000u;
-  return v;
+// LDS DMA: global_load_lds_dwordx4 moves 16 bytes per lane from global
+// memory straight into LDS, lane l writing bytes [16 l, 16 l + 16) after the
+// wave-uniform LDS address held in M0; the global address is a scalar base
+// plus a per-lane 32-bit byte offset.  It is issued as inline asm so that the
+// compiler, which cannot tell which LDS bytes an outstanding DMA writes, does
+// not wait for all of them before every LDS read; callers wait explicitly
+// (wait_vmem) before the barrier that publishes the data.
+template <typename T> __device__ inline T *uniform_ptr(T *p) {
+  const uint64_t v = (uint64_t)(uintptr_t)p;
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+  return (T *)(uintptr_t)(((uint64_t)hi << 32) | lo);
 }
-__device__ inline uint4 neg_f32x4(uint4 v) {
-  v.x ^= 0x80000000u;
-  v.y ^= 0x80000000u;
-  v.z ^= 0x80000000u;
-  v.w ^= 0x80000000u;
-  return v;
+typedef __attribute__((address_space(3))) void lds_void_t;
+__device__ inline void lds_dma16(const void *base, uint32_t voff, void *lds_dst) {
+  const uint32_t m0v = __builtin_amdgcn_readfirstlane((uint32_t)(uintptr_t)(lds_void_t *)lds_dst);
+  asm volatile("s_mov_b32 m0, %0\n\tglobal_load_lds_dwordx4 %1, %2" ::"s"(m0v), "v"(voff),
+               "s"(uniform_ptr(base))
+               : "memory", "m0");
 }
+__device__ inline void wait_vmem() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
 
-// ------------------------------------------------------------ FP64 / FP32 --
-template <int MODE>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void update_kernel(
-    typename Cfg<MODE>::T *__restrict__ tiles, int64_t N, int64_t p0, int pw, int64_t k0,
-    int64_t K, int mode, int S, int64_t G, int64_t G8, const int64_t *__restrict__ info) {
-  using C_ = Cfg<MODE>;
-  using T = typename C_::T;
-  using acc_t = typename C_::acc_t;
-  constexpr int KC = C_::KC;
-  constexpr int LDP = BT + C_::PAD;
-  constexpr int VE = 16 / sizeof(T);            // elements per 16-byte vector
-  constexpr int NV = KC * BT / VE / 256;        // 16-byte vectors per thread per operand
+// ------------------------------------------------------------------ FP32 --
+// FP32 storage and arithmetic on v_mfma_f32_16x16x4_f32.  Each wave owns a
+// 64 x 64 block as 4 x 4 MFMA blocks (s2, u).  MFMA row i of block s2 is
+// wave-local row 4i + s2 (and likewise column 4j + u), so a lane's four A
+// fragments (rows 4q .. 4q+3 at k = 4 ks + g) and four B fragments are one
+// 16-byte LDS read each, contiguous across lanes.  With the MFMA output
+// layout (lane (g, q), register e holds MFMA row 4g + e, column q) the
+// accumulator acc[s2][u][e] is C(64 wm + 16g + 4e + s2, 64 wn + 4q + u):
+// C moves as 16-byte vectors.  Chunks of 32 panel columns (128 bytes per tile
+// row) are DMA'd into unpadded LDS (the 16-byte fragment reads are
+// conflict-free without padding), two chunks ahead, with the same one-barrier
+// protocol as the FP64 kernel below (barrier after the second-to-last k-step
+// of a chunk).
+template <int REGION>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void update_f32_kernel(
+    float *__restrict__ tiles, int64_t N, int64_t p0, int pw, int64_t k0, int64_t K, int S,
+    int64_t G, int64_t G8, const int64_t *__restrict__ info) {
+  constexpr int KC = 32;        // panel columns per chunk
+  constexpr int NKS = KC / 4;   // k-steps per chunk
   if (*info != 0) return;
-
-  const int64_t bid = blockIdx.x;
-  const int64_t t = (bid % 8) * G8 + bid / 8;
-  if (t >= G) return;
-  int64_t ir, kr;
-  if (mode == 0)
-    map_triangle(t, N - k0, S, ir, kr);
-  else
-    map_band(t, K, ir, kr);
-  const int64_t i = k0 + ir, k = k0 + kr;
-
-  __shared__ __attribute__((aligned(16))) T lds[2][2][KC * LDP];
-
+  __shared__ __attribute__((aligned(16))) float lds[2][2][KC * BT];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int g = lane >> 4, q = lane & 15;
   const int wm = wave >> 1, wn = wave & 1;
+  const int wu = __builtin_amdgcn_readfirstlane(wave);
+  const int64_t per = gridDim.x / 8;  // persistent, as in the FP64 kernel
+  for (int64_t pos = blockIdx.x / 8; pos < G8; pos += per) {
+    const int64_t t = (blockIdx.x % 8) * G8 + pos;
+    if (t >= G) break;
+    int64_t ir, kr;
+    if (REGION == 0)
+      map_triangle(t, N - k0, S, ir, kr);
+    else
+      map_band(t, K, ir, kr);
+    const int64_t i = k0 + ir, k = k0 + kr;
+    float *C = tiles + tile_index(i, k, N) * (int64_t)(BT * BT);
+    const int nstage = pw * (BT / KC);
 
-  T *C = tiles + tile_index(i, k, N) * (int64_t)(BT * BT);
-
-  // Row interleave.  MFMA block s (of 4 per wave and dimension) takes, for
-  // its MFMA row index i, the wave-local row
-  //   FP64: 2i + (s & 1) + 32 (s >> 1)   -> a lane's fragments are rows
-  //         {2q, 2q+1} and {2q+32, 2q+33}: two 16-byte LDS reads that are
-  //         contiguous across the 16 lanes of a group (no bank conflicts);
-  //   FP32: 4i + s                       -> one 16-byte read {4q..4q+3}.
-  // Columns (the B operand) use the same map.  With the MFMA output layouts
-  // (lane (g,q), register e holds MFMA row g+4e for f64, 4g+e for f32, and
-  // MFMA column q), accumulator acc[s][u][e] is C element
-  //   row 64wm + crow(s, e),  column 64wn + ccol(u)
-  // with crow = 2g + 8e + (s&1) + 32(s>>1) (FP64) or 16g + 4e + s (FP32),
-  // ccol = 2q + (u&1) + 32(u>>1) (FP64) or 4q + u (FP32).  Consecutive s
-  // give consecutive rows, so C moves in 16-byte vectors.
-  auto crow = [&](int s4, int e) -> int {
-    return (MODE == 0) ? 2 * g + 8 * e + (s4 & 1) + 32 * (s4 >> 1) : 16 * g + 4 * e + s4;
-  };
-  auto ccol = [&](int u) -> int { return (MODE == 0) ? 2 * q + (u & 1) + 32 * (u >> 1) : 4 * q + u; };
-  constexpr int SPV = (MODE == 0) ? 2 : 4;  // consecutive s per 16-byte vector
-
-  acc_t acc[4][4];
+    // chunk s: 32 columns = 16 KB per operand = 16 one-KB column pairs;
+    // wave w moves pairs w, w+4, w+8, w+12 of both operands
+    auto dma = [&](int s) {
+      const int64_t p = p0 + (s * KC) / BT;
+      const int col0 = (s * KC) % BT;
+      const float *pa = tiles + tile_index(i, p, N) * (int64_t)(BT * BT) + col0 * BT;
+      const float *pb = tiles + tile_index(k, p, N) * (int64_t)(BT * BT) + col0 * BT;
 #pragma unroll
-  for (int u = 0; u < 4; ++u) {
-    const T *col = C + (64 * wn + ccol(u)) * BT + 64 * wm;
-#pragma unroll
-    for (int e = 0; e < 4; ++e)
-#pragma unroll
-      for (int s0 = 0; s0 < 4; s0 += SPV) {
-        T v[SPV];
-        *(uint4 *)&v[0] = *(const uint4 *)(col + crow(s0, e));
-#pragma unroll
-        for (int y = 0; y < SPV; ++y) acc[s0 + y][u][e] = v[y];
+      for (int c = 0; c < 4; ++c) {
+        const int off = (wu + 4 * c) * 2 * BT;
+        lds_dma16(pa + off, lane * 16, &lds[s & 1][0][off]);
+        lds_dma16(pb + off, lane * 16, &lds[s & 1][1][off]);
       }
-  }
+    };
 
-  const int nstage = pw * (BT / KC);
-  uint4 ra[NV], rb[NV];
-  auto gload = [&](int s) {
-    const int64_t p = p0 + (s * KC) / BT;
-    const int col0 = (s * KC) % BT;
-    const T *pa = tiles + tile_index(i, p, N) * (int64_t)(BT * BT) + col0 * BT;
-    const T *pb = tiles + tile_index(k, p, N) * (int64_t)(BT * BT) + col0 * BT;
+    v4f acc[4][4];
 #pragma unroll
-    for (int x = 0; x < NV; ++x) {
-      const int v = tid + 256 * x;
-      ra[x] = *(const uint4 *)(pa + v * VE);
-      rb[x] = *(const uint4 *)(pb + v * VE);
-    }
-  };
-  auto lstore = [&](int buf) {
+    for (int u = 0; u < 4; ++u) {
+      const float *col = C + (64 * wn + 4 * q + u) * BT + 64 * wm + 16 * g;
 #pragma unroll
-    for (int x = 0; x < NV; ++x) {
-      const int e = (tid + 256 * x) * VE;
-      const int kk = e / BT, r = e % BT;
-      uint4 na = (sizeof(T) == 8) ? neg_f64x2(ra[x]) : neg_f32x4(ra[x]);
-      *(uint4 *)&lds[buf][0][kk * LDP + r] = na;
-      *(uint4 *)&lds[buf][1][kk * LDP + r] = rb[x];
+      for (int e = 0; e < 4; ++e) {
+        float v[4];
+        *(uint4 *)&v[0] = *(const uint4 *)(col + 4 * e);
+#pragma unroll
+        for (int s2 = 0; s2 < 4; ++s2) acc[s2][u][e] = -v[s2];
+      }
     }
-  };
-  // fragments of k-step kk for this lane: a[s], b[u]
-  auto frag = [&](const T *la, const T *lb, int kk, T (&a)[4], T (&b)[4]) {
-    if constexpr (MODE == 0) {
-      *(uint4 *)&a[0] = *(const uint4 *)(la + kk * LDP + 64 * wm + 2 * q);
-      *(uint4 *)&a[2] = *(const uint4 *)(la + kk * LDP + 64 * wm + 2 * q + 32);
-      *(uint4 *)&b[0] = *(const uint4 *)(lb + kk * LDP + 64 * wn + 2 * q);
-      *(uint4 *)&b[2] = *(const uint4 *)(lb + kk * LDP + 64 * wn + 2 * q + 32);
-    } else {
-      *(uint4 *)&a[0] = *(const uint4 *)(la + kk * LDP + 64 * wm + 4 * q);
-      *(uint4 *)&b[0] = *(const uint4 *)(lb + kk * LDP + 64 * wn + 4 * q);
-    }
-  };
+    dma(0);
+    if (nstage > 1) dma(1);
+    wait_vmem();
+    __syncthreads();
 
-  gload(0);
-  lstore(0);
-  __syncthreads();
-  for (int s = 0; s < nstage; ++s) {
-    const int buf = s & 1;
-    if (s + 1 < nstage) gload(s + 1);
-    const T *la = &lds[buf][0][0];
-    const T *lb = &lds[buf][1][0];
-    T a[2][4], b[2][4];
-    frag(la, lb, g, a[0], b[0]);
-#pragma unroll
-    for (int ks = 0; ks < KC / 4; ++ks) {
-      const int cur = ks & 1;
-      if (ks + 1 < KC / 4) frag(la, lb, (ks + 1) * 4 + g, a[cur ^ 1], b[cur ^ 1]);
+    float fa[2][4], fb[2][4];
+    *(uint4 *)&fa[0][0] = *(const uint4 *)&lds[0][0][g * BT + 64 * wm + 4 * q];
+    *(uint4 *)&fb[0][0] = *(const uint4 *)&lds[0][1][g * BT + 64 * wn + 4 * q];
+    const int nk = nstage * NKS;
+    auto step = [&](int kt, int cur) {
+      const int s = kt / NKS, ks = kt % NKS;
+      const int nbuf = ((kt + 1) / NKS) & 1, nks = (kt + 1) % NKS;
+      // next k-step's fragments (stale but in-bounds after the last step)
+      *(uint4 *)&fa[cur ^ 1][0] = *(const uint4 *)&lds[nbuf][0][(4 * nks + g) * BT + 64 * wm + 4 * q];
+      *(uint4 *)&fb[cur ^ 1][0] = *(const uint4 *)&lds[nbuf][1][(4 * nks + g) * BT + 64 * wn + 4 * q];
 #pragma unroll
       for (int s2 = 0; s2 < 4; ++s2)
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          if constexpr (MODE == 0)
-            acc[s2][u] =
-                __builtin_amdgcn_mfma_f64_16x16x4f64(a[cur][s2], b[cur][u], acc[s2][u], 0, 0, 0);
-          else
-            acc[s2][u] =
-                __builtin_amdgcn_mfma_f32_16x16x4f32(a[cur][s2], b[cur][u], acc[s2][u], 0, 0, 0);
-        }
+        for (int u = 0; u < 4; ++u)
+          acc[s2][u] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[cur][s2], fb[cur][u], acc[s2][u], 0, 0, 0);
+      __builtin_amdgcn_sched_group_barrier(0x100, 2, 0);
+      __builtin_amdgcn_sched_group_barrier(0x008, 16, 0);
+      __builtin_amdgcn_sched_barrier(0);
+      if (ks == NKS - 2) {
+        wait_vmem();
+        __syncthreads();
+        if (s + 2 < nstage) dma(s + 2);
+      }
+    };
+    for (int kt = 0; kt < nk; kt += 2) {
+      step(kt, 0);
+      step(kt + 1, 1);
     }
-    if (s + 1 < nstage) lstore(buf ^ 1);
-    __syncthreads();
-  }
 
 #pragma unroll
-  for (int u = 0; u < 4; ++u) {
-    T *col = C + (64 * wn + ccol(u)) * BT + 64 * wm;
+    for (int u = 0; u < 4; ++u) {
+      float *col = C + (64 * wn + 4 * q + u) * BT + 64 * wm + 16 * g;
 #pragma unroll
-    for (int e = 0; e < 4; ++e)
+      for (int e = 0; e < 4; ++e) {
+        float v[4];
 #pragma unroll
-      for (int s0 = 0; s0 < 4; s0 += SPV) {
-        T v[SPV];
-#pragma unroll
-        for (int y = 0; y < SPV; ++y) v[y] = acc[s0 + y][u][e];
-        *(uint4 *)(col + crow(s0, e)) = *(const uint4 *)&v[0];
+        for (int s2 = 0; s2 < 4; ++s2) v[s2] = -acc[s2][u][e];
+        *(uint4 *)(col + 4 * e) = *(const uint4 *)&v[0];
       }
-  }
+    }
+  }  // tiles of this workgroup
 }
 
 // ---------------------------------------------------------- FP64, 4x4x4 --
@@ -234,102 +191,136 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void u
 // LDS reads, contiguous across lanes), its B fragments 16 single elements
 // that four lanes share (broadcast reads), and each C column is touched as
 // two 16-byte vectors.
+//
+// Staging: the panel chunks go from HBM straight into LDS with
+// global_load_lds_dwordx4 (no VGPR round trip, which frees the registers
+// for a second set of fragments), two chunks ahead.  The accumulators start
+// at -C and the tile is negated back on store, so the operands are staged
+// unmodified and every MFMA adds a b^T.  With fragments for k-step t+1 read
+// from LDS while the MFMAs of step t run, one barrier per chunk suffices,
+// placed after the third of its four k-steps:
+//   step 2 of chunk s: wait for this wave's DMA of chunk s+1, barrier B_s
+//                      (all waves have read chunk s's fragments and all DMA
+//                      of chunk s+1 has landed), then DMA chunk s+2 into
+//                      the buffer chunk s used;
+//   step 3 of chunk s: read the first fragments of chunk s+1.
+template <int REGION>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void update_f64_kernel(
-    double *__restrict__ tiles, int64_t N, int64_t p0, int pw, int64_t k0, int64_t K, int mode,
-    int S, int64_t G, int64_t G8, const int64_t *__restrict__ info) {
-  constexpr int KC = 16;          // panel columns per LDS chunk (128 bytes per tile row)
-  constexpr int LDP = BT + 4;     // LDS row pitch (doubles)
-  constexpr int NV = KC * BT / 2 / 256;  // 16-byte vectors per thread per operand
+    double *__restrict__ tiles, int64_t N, int64_t p0, int pw, int64_t k0, int64_t K, int S,
+    int64_t G, int64_t G8, const int64_t *__restrict__ info) {
+  constexpr int KC = 16;       // panel columns per LDS chunk (128 bytes per tile row)
+  constexpr int LDP = BT + 4;  // LDS row pitch (doubles)
   if (*info != 0) return;
-  const int64_t bid = blockIdx.x;
-  const int64_t t = (bid % 8) * G8 + bid / 8;
-  if (t >= G) return;
-  int64_t ir, kr;
-  if (mode == 0)
-    map_triangle(t, N - k0, S, ir, kr);
-  else
-    map_band(t, K, ir, kr);
-  const int64_t i = k0 + ir, k = k0 + kr;
-
   __shared__ __attribute__((aligned(16))) double lds[2][2][KC * LDP];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int g = lane >> 4, q = lane & 15, bq = q >> 2, jq = q & 3;
   const int wm = wave >> 1, wn = wave & 1;
-  double *C = tiles + tile_index(i, k, N) * (int64_t)(BT * BT);
+  const int wu = __builtin_amdgcn_readfirstlane(wave);
+  // Persistent: workgroup w walks the tiles of XCD range w mod 8 (positions
+  // w/8, w/8 + per, ...), so the grid may be smaller than the tile count.
+  const int64_t per = gridDim.x / 8;
+  for (int64_t pos = blockIdx.x / 8; pos < G8; pos += per) {
+    const int64_t t = (blockIdx.x % 8) * G8 + pos;
+    if (t >= G) break;
+    int64_t ir, kr;
+    if (REGION == 0)
+      map_triangle(t, N - k0, S, ir, kr);
+    else
+      map_band(t, K, ir, kr);
+    const int64_t i = k0 + ir, k = k0 + kr;
+    double *C = tiles + tile_index(i, k, N) * (int64_t)(BT * BT);
+    const int nstage = pw * (BT / KC);
 
-  // acc[x][y] <-> C(64wm + 8bq + 2g + (x&1) + 32(x>>1), 64wn + 4y + jq)
-  double acc[4][16];
+    // chunk s = columns [16 s mod 128, +16) of panel tile p0 + 16 s / 128;
+    // wave w moves columns w, w+4, w+8, w+12 of both operands (1 KB each)
+    auto dma = [&](int s) {
+      const int64_t p = p0 + (s * KC) / BT;
+      const int col0 = (s * KC) % BT;
+      const double *pa = tiles + tile_index(i, p, N) * (int64_t)(BT * BT) + col0 * BT;
+      const double *pb = tiles + tile_index(k, p, N) * (int64_t)(BT * BT) + col0 * BT;
 #pragma unroll
-  for (int y = 0; y < 16; ++y) {
-    const double *col = C + (64 * wn + 4 * y + jq) * BT + 64 * wm + 8 * bq + 2 * g;
-#pragma unroll
-    for (int xh = 0; xh < 2; ++xh) {
-      double v[2];
-      *(uint4 *)&v[0] = *(const uint4 *)(col + 32 * xh);
-      acc[2 * xh][y] = v[0];
-      acc[2 * xh + 1][y] = v[1];
-    }
-  }
+      for (int c = 0; c < KC / 4; ++c) {
+        const int kk = wu + 4 * c;
+        lds_dma16(pa + kk * BT, lane * 16, &lds[s & 1][0][kk * LDP]);
+        lds_dma16(pb + kk * BT, lane * 16, &lds[s & 1][1][kk * LDP]);
+      }
+    };
 
-  const int nstage = pw * (BT / KC);
-  uint4 ra[NV], rb[NV];
-  auto gload = [&](int s) {
-    const int64_t p = p0 + (s * KC) / BT;
-    const int col0 = (s * KC) % BT;
-    const double *pa = tiles + tile_index(i, p, N) * (int64_t)(BT * BT) + col0 * BT;
-    const double *pb = tiles + tile_index(k, p, N) * (int64_t)(BT * BT) + col0 * BT;
+    // acc[x][y] <-> -C(64wm + 8bq + 2g + (x&1) + 32(x>>1), 64wn + 4y + jq)
+    double acc[4][16];
 #pragma unroll
-    for (int x = 0; x < NV; ++x) {
-      const int v = tid + 256 * x;
-      ra[x] = *(const uint4 *)(pa + v * 2);
-      rb[x] = *(const uint4 *)(pb + v * 2);
-    }
-  };
-  auto lstore = [&](int buf) {
+    for (int y = 0; y < 16; ++y) {
+      const double *col = C + (64 * wn + 4 * y + jq) * BT + 64 * wm + 8 * bq + 2 * g;
 #pragma unroll
-    for (int x = 0; x < NV; ++x) {
-      const int e = (tid + 256 * x) * 2;
-      const int kk = e / BT, r = e % BT;
-      *(uint4 *)&lds[buf][0][kk * LDP + r] = neg_f64x2(ra[x]);
-      *(uint4 *)&lds[buf][1][kk * LDP + r] = rb[x];
+      for (int xh = 0; xh < 2; ++xh) {
+        double v[2];
+        *(uint4 *)&v[0] = *(const uint4 *)(col + 32 * xh);
+        acc[2 * xh][y] = -v[0];
+        acc[2 * xh + 1][y] = -v[1];
+      }
     }
-  };
+    dma(0);
+    if (nstage > 1) dma(1);
+    wait_vmem();
+    __syncthreads();
 
-  gload(0);
-  lstore(0);
-  __syncthreads();
-  for (int s = 0; s < nstage; ++s) {
-    const int buf = s & 1;
-    if (s + 1 < nstage) gload(s + 1);
-    const double *la = &lds[buf][0][64 * wm + 2 * q];
-    const double *lb = &lds[buf][1][64 * wn + jq];
+    // fa[buf]: A fragments of the current / next k-step; fb: B fragments,
+    // each overwritten with the next step's value once its 4 MFMAs are issued
+    double fa[2][4], fb[16];
+    {
+      const double *la = &lds[0][0][64 * wm + 2 * q + g * LDP];
+      const double *lb = &lds[0][1][64 * wn + jq + g * LDP];
+      *(uint4 *)&fa[0][0] = *(const uint4 *)(la);
+      *(uint4 *)&fa[0][2] = *(const uint4 *)(la + 32);
 #pragma unroll
-    for (int ks = 0; ks < KC / 4; ++ks) {
-      const int kk = ks * 4 + g;
-      double a[4], b[16];
-      *(uint4 *)&a[0] = *(const uint4 *)(la + kk * LDP);
-      *(uint4 *)&a[2] = *(const uint4 *)(la + kk * LDP + 32);
+      for (int y = 0; y < 16; ++y) fb[y] = lb[4 * y];
+    }
+    const int nk = nstage * (KC / 4);
+    auto step = [&](int kt, int cur) {
+      const int s = kt >> 2, ks = kt & 3;
+      // next k-step's fragments (after the last step this reads stale but
+      // in-bounds LDS; the values are not used)
+      const int nbuf = ((kt + 1) >> 2) & 1, nks = (kt + 1) & 3;
+      const double *la = &lds[nbuf][0][64 * wm + 2 * q + (nks * 4 + g) * LDP];
+      const double *lb = &lds[nbuf][1][64 * wn + jq + (nks * 4 + g) * LDP];
+      *(uint4 *)&fa[cur ^ 1][0] = *(const uint4 *)(la);
+      *(uint4 *)&fa[cur ^ 1][2] = *(const uint4 *)(la + 32);
 #pragma unroll
-      for (int y = 0; y < 16; ++y) b[y] = lb[kk * LDP + 4 * y];
-#pragma unroll
-      for (int y = 0; y < 16; ++y)
+      for (int y = 0; y < 16; ++y) {
 #pragma unroll
         for (int x = 0; x < 4; ++x)
-          acc[x][y] = __builtin_amdgcn_mfma_f64_4x4x4f64(a[x], b[y], acc[x][y], 0, 0, 0);
+          acc[x][y] = __builtin_amdgcn_mfma_f64_4x4x4f64(fa[cur][x], fb[y], acc[x][y], 0, 0, 0);
+        fb[y] = lb[4 * y];
+      }
+      // interleave: the two A reads first, then one B read per 4 MFMAs
+      __builtin_amdgcn_sched_group_barrier(0x100, 2, 0);
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        __builtin_amdgcn_sched_group_barrier(0x008, 4, 0);
+        __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+      }
+      __builtin_amdgcn_sched_barrier(0);
+      if (ks == 2) {
+        wait_vmem();
+        __syncthreads();
+        if (s + 2 < nstage) dma(s + 2);
+      }
+    };
+    for (int kt = 0; kt < nk; kt += 2) {
+      step(kt, 0);
+      step(kt + 1, 1);
     }
-    if (s + 1 < nstage) lstore(buf ^ 1);
-    __syncthreads();
-  }
 
 #pragma unroll
-  for (int y = 0; y < 16; ++y) {
-    double *col = C + (64 * wn + 4 * y + jq) * BT + 64 * wm + 8 * bq + 2 * g;
+    for (int y = 0; y < 16; ++y) {
+      double *col = C + (64 * wn + 4 * y + jq) * BT + 64 * wm + 8 * bq + 2 * g;
 #pragma unroll
-    for (int xh = 0; xh < 2; ++xh) {
-      double v[2] = {acc[2 * xh][y], acc[2 * xh + 1][y]};
-      *(uint4 *)(col + 32 * xh) = *(const uint4 *)&v[0];
+      for (int xh = 0; xh < 2; ++xh) {
+        double v[2] = {-acc[2 * xh][y], -acc[2 * xh + 1][y]};
+        *(uint4 *)(col + 32 * xh) = *(const uint4 *)&v[0];
+      }
     }
-  }
+  }  // tiles of this workgroup
 }
 
 // --------------------------------------------------- FP16 operands (FP32 C) --
@@ -344,9 +335,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void u
   constexpr int KC16 = 32;            // k per chunk
   constexpr int RP = KC16 + 8;        // LDS row pitch in halves (80 bytes)
   if (*info != 0) return;
-  const int64_t bid = blockIdx.x;
-  const int64_t t = (bid % 8) * G8 + bid / 8;
-  if (t >= G) return;
+  __shared__ __attribute__((aligned(16))) _Float16 lds[2][2][BT * RP];
+  // Persistent: workgroup w walks the tiles of XCD range w mod 8 (positions
+  // w/8, w/8 + per, ...), so the grid may be smaller than the tile count.
+  const int64_t per = gridDim.x / 8;
+  for (int64_t pos = blockIdx.x / 8; pos < G8; pos += per) {
+  const int64_t t = (blockIdx.x % 8) * G8 + pos;
+  if (t >= G) break;
   int64_t ir, kr;
   if (mode == 0)
     map_triangle(t, N - k0, S, ir, kr);
@@ -354,7 +349,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void u
     map_band(t, K, ir, kr);
   const int64_t i = k0 + ir, k = k0 + kr;
 
-  __shared__ __attribute__((aligned(16))) _Float16 lds[2][2][BT * RP];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int g = lane >> 4, q = lane & 15;
   const int wm = wave >> 1, wn = wave & 1;
@@ -437,6 +431,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void u
       for (int x = 0; x < 4; ++x) *(uint4 *)(dst + x * 4) = *(const uint4 *)&v[x * 4];
     }
   }
+  }  // tiles of this workgroup
 }
 
 // Portable fallback for tile side 64 (small problems): one workgroup of 256
@@ -490,7 +485,7 @@ __global__ __launch_bounds__(256) void update64_kernel(T *__restrict__ tiles, in
 
 void launch_update(void *tiles, int store, int b, int64_t N, int64_t p0, int pw, int64_t k0,
                    int64_t k1, int mode, int super_tile, int fp16, const int64_t *info,
-                   hipStream_t s) {
+                   hipStream_t s, int64_t max_wg) {
   const int64_t R = N - k0;
   if (R <= 0 || pw <= 0) return;
   const int64_t K = k1 - k0;
@@ -504,16 +499,24 @@ void launch_update(void *tiles, int store, int b, int64_t N, int64_t p0, int pw,
   if (G <= 0) return;
   if (b == BT) {
     const int64_t G8 = (G + 7) / 8;
-    const dim3 grid((unsigned)(8 * G8));
+    int64_t nwg = 8 * G8;
+    if (max_wg >= 8 && nwg > max_wg) nwg = (max_wg / 8) * 8;  // persistent: fewer workgroups
+    const dim3 grid((unsigned)nwg);
     if (fp16)
       hipLaunchKernelGGL(update_f16_kernel, grid, dim3(256), 0, s, (float *)tiles, N, p0, pw, k0,
                          K, mode, super_tile, G, G8, info);
+    else if (store == STORE_F64 && mode == 0)
+      hipLaunchKernelGGL(update_f64_kernel<0>, grid, dim3(256), 0, s, (double *)tiles, N, p0, pw,
+                         k0, K, super_tile, G, G8, info);
     else if (store == STORE_F64)
-      hipLaunchKernelGGL(update_f64_kernel, grid, dim3(256), 0, s, (double *)tiles, N, p0, pw, k0,
-                         K, mode, super_tile, G, G8, info);
+      hipLaunchKernelGGL(update_f64_kernel<1>, grid, dim3(256), 0, s, (double *)tiles, N, p0, pw,
+                         k0, K, super_tile, G, G8, info);
+    else if (mode == 0)
+      hipLaunchKernelGGL(update_f32_kernel<0>, grid, dim3(256), 0, s, (float *)tiles, N, p0, pw,
+                         k0, K, super_tile, G, G8, info);
     else
-      hipLaunchKernelGGL(update_kernel<1>, grid, dim3(256), 0, s, (float *)tiles, N, p0, pw, k0,
-                         K, mode, super_tile, G, G8, info);
+      hipLaunchKernelGGL(update_f32_kernel<1>, grid, dim3(256), 0, s, (float *)tiles, N, p0, pw,
+                         k0, K, super_tile, G, G8, info);
   } else {
     const dim3 grid((unsigned)G);
     if (store == STORE_F64)
