@@ -102,7 +102,8 @@ int gp_assemble(const double *X, int64_t n, int64_t d, int64_t ldx,
  * at the given precision and tile (tile 0 = the tuned default).  The factor
  * is stored as the paper stores it (Implementation section): only the
  * lower-triangular and diagonal square blocks, each block contiguous, plus
- * a transposed copy of the N diagonal blocks for the back substitution.
+ * the N inverted diagonal blocks L_cc^{-T} that the solves apply (computed
+ * once at the end of the factorisation).
  * Returns 0 for invalid arguments.  Host-only; no device work.           */
 size_t chol_factor_bytes(int64_t n, int precision, int tile);
 
@@ -157,8 +158,15 @@ int chol_get_info(chol_handle F, int64_t *info);
 /* ---- chol_solve --------------------------------------------------------
  * B <- A^{-1} B using the factor only: forward substitution L Y = B, then
  * back substitution L^T X = Y (Fundamentals, "The Cholesky decomposition").
- * Arithmetic is FP64 whatever the factor's storage precision.
+ * Arithmetic is FP64 whatever the factor's storage precision.  Blocked by
+ * tiles: block row i is b_i minus the products with the finished blocks,
+ * times the inverted diagonal block, in one kernel launch per direction.
  * B : device, n x nrhs column-major FP64, ldb >= max(1, n), overwritten.
+ * Uses a small per-(device, stream) synchronisation buffer that the library
+ * allocates on the first call from a stream; when called under stream
+ * capture, call it once on that stream before capturing.  Each wait between
+ * workgroups is bounded (option "solve_spin_max"); should a bound ever run
+ * out, the affected rows of B are set to NaN instead of hanging.
  * Errors: CHOL_ERR_BAD_HANDLE, -2 B NULL with nrhs > 0, -3 nrhs < 0,
  * -4 ldb, CHOL_ERR_NOT_SPD if the factorisation reported info > 0.       */
 int chol_solve(chol_handle F, double *B, int64_t nrhs, int64_t ldb,
@@ -252,6 +260,8 @@ void chol_profile_reset(void);
  *                  Not used for CHOL_FP16_SCALED or while profiling.
  * "profile"      : 1 records kernel timing, 2 only of the triangle launches
  *                  (see chol_profile_read).
+ * "solve_spin_max": polls allowed per wait inside chol_solve (default 2^20,
+ *                  about a second; rows of a solve that runs out become NaN).
  * "bulk_wg_cap"  : with lookahead, the far trailing update runs with at most
  *                  this many (persistent) workgroups, leaving slots for the
  *                  next panel's kernels (default 0 = no cap: one workgroup

@@ -40,6 +40,7 @@ struct Options {
   std::atomic<int64_t> graph{0};
   std::atomic<int64_t> profile{0};
   std::atomic<int64_t> bulk_wg_cap{0};  // workgroups of the bulk update under lookahead (0 = all)
+  std::atomic<int64_t> solve_spin_max{1 << 20};  // bound of each wait inside a solve
 };
 Options g_opt;
 
@@ -47,11 +48,15 @@ Options g_opt;
 // stream), created on first use and kept until the process ends, so that
 // factorisations issued concurrently on different caller streams (e.g. by
 // the serving loop's worker threads) never share them.
+// The same context holds the solves' synchronisation words (an abort flag
+// and per-chunk progress counters, cleared by a kernel before every solve).
+constexpr int64_t kSyncWords = 4096;
 struct SideCtx {
   int device = -1;
   hipStream_t caller = nullptr;
   hipStream_t side = nullptr;
   hipEvent_t ev_fork = nullptr, ev_panel = nullptr, ev_bulk = nullptr, ev_join = nullptr;
+  int *sync = nullptr;  // kSyncWords ints of device memory
 };
 std::mutex g_ctx_mu;
 std::vector<SideCtx *> g_ctx;
@@ -78,6 +83,7 @@ int get_ctx(hipStream_t caller, SideCtx **out) {
       hipEventCreateWithFlags(&c->ev_bulk, fl) != hipSuccess ||
       hipEventCreateWithFlags(&c->ev_join, fl) != hipSuccess)
     return CHOL_ERR_HIP;
+  if (hipMalloc((void **)&c->sync, kSyncWords * sizeof(int)) != hipSuccess) return CHOL_ERR_HIP;
   g_ctx.push_back(c);
   *out = c;
   return CHOL_OK;
@@ -173,7 +179,7 @@ struct chol_factor_s {
   int64_t n = 0, N = 0;
   int b = 0, precision = 0, device = 0;
   void *tiles = nullptr;
-  void *diag_t = nullptr;  // transposed diagonal blocks (back substitution)
+  void *dinv = nullptr;  // inverted diagonal blocks L_cc^{-T} (the solves)
   int64_t *d_info = nullptr;
   double scale = 1.0;  // CHOL_FP16_SCALED: the factor of A / scale is stored
   hipStream_t stream = nullptr;
@@ -219,6 +225,9 @@ int chol_set_option(const char *key, int64_t value) {
   } else if (!strcmp(key, "profile")) {
     if (value < 0 || value > 2) return -2;
     g_opt.profile = value;
+  } else if (!strcmp(key, "solve_spin_max")) {
+    if (value < 1 || value > (int64_t)1 << 30) return -2;
+    g_opt.solve_spin_max = value;
   } else if (!strcmp(key, "bulk_wg_cap")) {
     if (value < 0 || value > (int64_t)1 << 30) return -2;
     g_opt.bulk_wg_cap = value;
@@ -236,6 +245,7 @@ int64_t chol_get_option(const char *key) {
   if (!strcmp(key, "graph")) return g_opt.graph;
   if (!strcmp(key, "profile")) return g_opt.profile;
   if (!strcmp(key, "bulk_wg_cap")) return g_opt.bulk_wg_cap;
+  if (!strcmp(key, "solve_spin_max")) return g_opt.solve_spin_max;
   return -1;
 }
 
@@ -307,7 +317,7 @@ static void factor_panel(chol_factor_s *F, int64_t c0, int64_t c1, int st, hipSt
   const int b = F->b;
   const int fp16 = F->precision == CHOL_FP16_SCALED;
   for (int64_t c = c0; c < c1; ++c) {
-    launch_potrf(F->tiles, st, b, N, c, F->diag_t, F->d_info, s);
+    launch_potrf(F->tiles, st, b, N, c, F->d_info, s);
     launch_trsm(F->tiles, st, b, N, c, F->d_info, s);
     if (c + 1 < c1)
       update(F->tiles, st, b, N, c, 1, c + 1, c1, /*band*/ 1, 8, fp16, F->d_info, s);
@@ -360,6 +370,8 @@ static int enqueue_factor(chol_factor_s *F, SideCtx *ctx, const double *A, int64
     HIP_OK(hipEventRecord(ctx->ev_join, p));
     HIP_OK(hipStreamWaitEvent(s, ctx->ev_join, 0));
   }
+  // inverted diagonal blocks for the solves
+  launch_diag_inverse(F->tiles, st, b, N, F->dinv, F->d_info, s);
   return hipGetLastError() == hipSuccess ? CHOL_OK : CHOL_ERR_HIP;
 }
 
@@ -399,7 +411,7 @@ int chol_factor_ex(const double *A, int64_t n, int64_t lda, int precision,
   (void)hipGetDevice(&F->device);
   F->d_info = (int64_t *)workspace;
   F->tiles = (char *)workspace + kHeader;
-  F->diag_t = (char *)F->tiles + (size_t)tile_count(F->N) * (size_t)tile * tile * esize_of(precision);
+  F->dinv = (char *)F->tiles + (size_t)tile_count(F->N) * (size_t)tile * tile * esize_of(precision);
   F->stream = (hipStream_t)stream;
   const int st = store_of(precision);
   const int64_t N = F->N;
@@ -533,8 +545,12 @@ int chol_solve(chol_handle F, double *B, int64_t nrhs, int64_t ldb, void *stream
   if (F->info > 0) return CHOL_ERR_NOT_SPD;
   hipStream_t s = (hipStream_t)stream;
   const int st = store_of(F->precision);
-  launch_trsv_fwd(F->tiles, F->diag_t, st, F->b, F->N, F->n, B, ldb, nrhs, s);
-  launch_trsv_bwd(F->tiles, F->diag_t, st, F->b, F->N, F->n, B, ldb, nrhs, s);
+  if (F->n == 0 || nrhs == 0) return CHOL_OK;
+  SideCtx *ctx = nullptr;
+  const int rc = get_ctx(s, &ctx);
+  if (rc) return rc;
+  launch_solve(F->tiles, F->dinv, st, F->b, F->N, F->n, B, ldb, nrhs, ctx->sync, kSyncWords,
+               (int)g_opt.solve_spin_max.load(), s);
   if (F->scale != 1.0) launch_scale(B, F->n, ldb, nrhs, 1.0 / F->scale, s);
   return hipGetLastError() == hipSuccess ? CHOL_OK : CHOL_ERR_HIP;
 }

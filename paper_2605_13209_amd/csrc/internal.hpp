@@ -48,10 +48,9 @@ void launch_pack(const double *A, int64_t n, int64_t lda, void *tiles, int store
 void launch_unpack(const void *tiles, int store, int b, int64_t N, int64_t n, double scale,
                    double *L, int64_t ldl, hipStream_t s);
 
-// Step 1: factor diagonal tile c in place (FP64 arithmetic) and store its
-// transpose as block c of diag_t (N blocks of b x b).  Sets *info.
-void launch_potrf(void *tiles, int store, int b, int64_t N, int64_t c, void *diag_t,
-                  int64_t *info, hipStream_t s);
+// Step 1: factor diagonal tile c in place (FP64 arithmetic).  Sets *info.
+void launch_potrf(void *tiles, int store, int b, int64_t N, int64_t c, int64_t *info,
+                  hipStream_t s);
 // Step 2: tiles (i, c), i in [c+1, N): X <- X L_cc^{-T} (FP64 arithmetic).
 void launch_trsm(void *tiles, int store, int b, int64_t N, int64_t c, const int64_t *info,
                  hipStream_t s);
@@ -65,12 +64,16 @@ void launch_update(void *tiles, int store, int b, int64_t N, int64_t p0, int pw,
                    int64_t k1, int mode, int super_tile, int fp16, const int64_t *info,
                    hipStream_t s, int64_t max_wg = 0);
 
-// Triangular solves, in place on B (n x nrhs, ldb), FP64 arithmetic.  The
-// back substitution reads the transposed diagonal blocks from diag_t.
-void launch_trsv_fwd(const void *tiles, const void *diag_t, int store, int b, int64_t N,
-                     int64_t n, double *B, int64_t ldb, int64_t nrhs, hipStream_t s);
-void launch_trsv_bwd(const void *tiles, const void *diag_t, int store, int b, int64_t N,
-                     int64_t n, double *B, int64_t ldb, int64_t nrhs, hipStream_t s);
+// After the factorisation: block c of dinv (N blocks of b x b) = L_cc^{-T}.
+void launch_diag_inverse(const void *tiles, int store, int b, int64_t N, void *dinv,
+                         const int64_t *info, hipStream_t s);
+// Forward then back substitution, in place on B (n x nrhs, ldb), FP64
+// arithmetic, one launch per direction (and per group of right-hand sides).
+// sync: device scratch of sync_words ints (>= 3), cleared by the launcher;
+// spin_max bounds each inter-workgroup wait (rows of an aborted solve are NaN).
+void launch_solve(const void *tiles, const void *dinv, int store, int b, int64_t N, int64_t n,
+                  double *B, int64_t ldb, int64_t nrhs, int *sync, int64_t sync_words,
+                  int spin_max, hipStream_t s);
 // Scale B by alpha in place (used by the scaled-FP16 factor).
 void launch_scale(double *B, int64_t n, int64_t ldb, int64_t nrhs, double alpha, hipStream_t s);
 

@@ -6,7 +6,9 @@
 // Both always compute in FP64, whatever the storage precision of the tiles;
 // results are rounded to the storage type on the way out.  Both use
 // substitution (no explicit inverse), so a factor whose entries are exact
-// small integers is reproduced bit for bit.
+// small integers is reproduced bit for bit.  The same substitution applied
+// to the identity gives the inverted diagonal blocks L_cc^{-T} that the
+// triangular solves use (diag_inverse_kernel, run once after the factorisation).
 #include "internal.hpp"
 
 namespace chol {
@@ -27,12 +29,9 @@ namespace {
 // blocks that are inactive at block km are skipped at compile time.  The tile
 // is moved between HBM and registers through LDS, half a tile at a time (so
 // the kernel's LDS fits next to a trailing-update workgroup on one CU), with
-// contiguous global accesses.  The kernel also stores L_cc^T (column-major) in a
-// side array, so that the back substitution reads the diagonal blocks along
-// columns as well.
+// contiguous global accesses.
 template <int B, typename T>
 __global__ __launch_bounds__(256) void potrf_kernel(T *__restrict__ tiles, int64_t N, int64_t c,
-                                                    T *__restrict__ diag_t,
                                                     int64_t *__restrict__ info) {
   if (*info != 0) return;
   constexpr int M = B / 16;
@@ -101,7 +100,6 @@ __global__ __launch_bounds__(256) void potrf_kernel(T *__restrict__ tiles, int64
       }
     }
   }
-  T *tt = diag_t + c * (int64_t)(B * B);  // L_cc^T, used by the back substitution
 #pragma unroll
   for (int hf = 0; hf < 2; ++hf) {
     __syncthreads();
@@ -113,14 +111,9 @@ __global__ __launch_bounds__(256) void potrf_kernel(T *__restrict__ tiles, int64
         stage[(j - hf * HC) * LD + i] = (i >= j) ? a[m][n] : 0.0;
       }
     __syncthreads();
-    // columns hf*HC.. of L, and the same rows of L^T
     for (int e = t; e < HC * B; e += 256) {
       const int r = e % B, cc = e / B;
       tile[(hf * HC + cc) * B + r] = (T)stage[cc * LD + r];
-    }
-    for (int e = t; e < HC * B; e += 256) {
-      const int cc = e % HC, r = e / HC;  // L^T(r', c') = L(c', r'): row r of L^T, column hf*HC+cc
-      tt[(hf * HC + cc) + (int64_t)r * B] = (T)stage[cc * LD + r];
     }
   }
 }
@@ -138,16 +131,13 @@ __global__ __launch_bounds__(256) void potrf_kernel(T *__restrict__ tiles, int64
 //   the owner of block q adds the H partial sums (in a fixed order) to the
 //   right-hand side and solves the 16 x 16 triangle by substitution,
 //   multiplying by reciprocals of the diagonal.
-template <int B, typename T>
-__global__ __launch_bounds__(256) void trsm_kernel(T *__restrict__ tiles, int64_t N, int64_t c,
-                                                   const int64_t *__restrict__ info) {
-  if (*info != 0) return;
+// IDENT: the right-hand side is the identity (X is only written), which gives
+// X = L^{-T}: used for the inverted diagonal blocks of the solves.
+template <int B, typename T, bool IDENT>
+__device__ __forceinline__ void trsm_tile(const T *__restrict__ L, T *__restrict__ X) {
   constexpr int CB = 16, NB = B / CB, H = 256 / B;
   __shared__ double ls[2][B * CB];         // ls[.][m * CB + u] = L[16q + u][m]
   __shared__ double part[H][CB][B + 1];    // partial sums per (h, u, row)
-  const int64_t i = c + 1 + blockIdx.x;
-  const T *L = tiles + tile_index(c, c, N) * (int64_t)(B * B);
-  T *X = tiles + tile_index(i, c, N) * (int64_t)(B * B);
   const int t = threadIdx.x, r = t % B, h = t / B;
   // strip q: elements e < (q + 1) * CB * CB, e = m * CB + u -> L[m * B + 16q + u]
   for (int e = t; e < CB * CB; e += 256) ls[0][e] = (double)L[(e / CB) * B + (e % CB)];
@@ -191,7 +181,8 @@ __global__ __launch_bounds__(256) void trsm_kernel(T *__restrict__ tiles, int64_
         double s = part[0][u][r];
 #pragma unroll
         for (int hh = 1; hh < H; ++hh) s += part[hh][u][r];
-        v[u] = (double)X[(q * CB + u) * B + r] - s;
+        const double rhs = IDENT ? (q * CB + u == r ? 1.0 : 0.0) : (double)X[(q * CB + u) * B + r];
+        v[u] = rhs - s;
       }
 #pragma unroll
       for (int u = 0; u < CB; ++u) {
@@ -213,15 +204,35 @@ __global__ __launch_bounds__(256) void trsm_kernel(T *__restrict__ tiles, int64_
   }
 }
 
+template <int B, typename T>
+__global__ __launch_bounds__(256) void trsm_kernel(T *__restrict__ tiles, int64_t N, int64_t c,
+                                                   const int64_t *__restrict__ info) {
+  if (*info != 0) return;
+  const int64_t i = c + 1 + blockIdx.x;
+  trsm_tile<B, T, false>(tiles + tile_index(c, c, N) * (int64_t)(B * B),
+                         tiles + tile_index(i, c, N) * (int64_t)(B * B));
+}
+
+// Inverted diagonal blocks for the solves: block c of dinv = L_cc^{-T}
+// (column-major), one workgroup per diagonal tile.
+template <int B, typename T>
+__global__ __launch_bounds__(256) void diag_inverse_kernel(const T *__restrict__ tiles, int64_t N,
+                                                           T *__restrict__ dinv,
+                                                           const int64_t *__restrict__ info) {
+  if (*info != 0) return;
+  const int64_t c = blockIdx.x;
+  trsm_tile<B, T, true>(tiles + tile_index(c, c, N) * (int64_t)(B * B),
+                        dinv + c * (int64_t)(B * B));
+}
+
 template <int B>
-void potrf_dispatch(void *tiles, int store, int64_t N, int64_t c, void *diag_t, int64_t *info,
-                    hipStream_t s) {
+void potrf_dispatch(void *tiles, int store, int64_t N, int64_t c, int64_t *info, hipStream_t s) {
   if (store == STORE_F64)
     hipLaunchKernelGGL((potrf_kernel<B, double>), dim3(1), dim3(256), 0, s, (double *)tiles, N, c,
-                       (double *)diag_t, info);
+                       info);
   else
     hipLaunchKernelGGL((potrf_kernel<B, float>), dim3(1), dim3(256), 0, s, (float *)tiles, N, c,
-                       (float *)diag_t, info);
+                       info);
 }
 
 template <int B>
@@ -239,12 +250,33 @@ void trsm_dispatch(void *tiles, int store, int64_t N, int64_t c, const int64_t *
 
 }  // namespace
 
-void launch_potrf(void *tiles, int store, int b, int64_t N, int64_t c, void *diag_t,
-                  int64_t *info, hipStream_t s) {
+void launch_potrf(void *tiles, int store, int b, int64_t N, int64_t c, int64_t *info,
+                  hipStream_t s) {
   if (b == 128)
-    potrf_dispatch<128>(tiles, store, N, c, diag_t, info, s);
+    potrf_dispatch<128>(tiles, store, N, c, info, s);
   else
-    potrf_dispatch<64>(tiles, store, N, c, diag_t, info, s);
+    potrf_dispatch<64>(tiles, store, N, c, info, s);
+}
+
+void launch_diag_inverse(const void *tiles, int store, int b, int64_t N, void *dinv,
+                         const int64_t *info, hipStream_t s) {
+  if (N <= 0) return;
+  const dim3 grid((unsigned)N);
+  if (b == 128) {
+    if (store == STORE_F64)
+      hipLaunchKernelGGL((diag_inverse_kernel<128, double>), grid, dim3(256), 0, s,
+                         (const double *)tiles, N, (double *)dinv, info);
+    else
+      hipLaunchKernelGGL((diag_inverse_kernel<128, float>), grid, dim3(256), 0, s,
+                         (const float *)tiles, N, (float *)dinv, info);
+  } else {
+    if (store == STORE_F64)
+      hipLaunchKernelGGL((diag_inverse_kernel<64, double>), grid, dim3(256), 0, s,
+                         (const double *)tiles, N, (double *)dinv, info);
+    else
+      hipLaunchKernelGGL((diag_inverse_kernel<64, float>), grid, dim3(256), 0, s,
+                         (const float *)tiles, N, (float *)dinv, info);
+  }
 }
 
 void launch_trsm(void *tiles, int store, int b, int64_t N, int64_t c, const int64_t *info,

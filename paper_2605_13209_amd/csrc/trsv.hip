@@ -3,199 +3,309 @@
 //   L Y = B  (forward),   L^T X = Y  (back),   in place on B (n x nrhs).
 // Arithmetic is FP64; FP32 factor tiles are widened on load.
 //
-// One launch per tile step s (blocked substitution, right-looking):
-//   forward step s : workgroup 0 applies tile (s, s-1) to block row s and
-//                    then solves the diagonal block L_ss y_s = b_s; every
-//                    other workgroup w applies tile (s+w, s-1) to block row
-//                    s+w.  So block row s is final exactly when step s solves
-//                    it, and every launch reads one column of tiles.
-//   back step s    : the mirror image with the transposed tiles of block
-//                    row s+1, solving L_ss^T x_s = y_s with the transposed
-//                    copy of the diagonal block kept by the factorisation.
-// Each workgroup first copies its whole tile into LDS with contiguous column
-// reads (one memory latency per tile), then works from LDS.  The diagonal
-// solve is one wave per right-hand side: the finished value of row r is
-// broadcast from its lane (readlane) and the other rows are updated with
-// column r of the block, read from LDS ahead of use.  Padding rows (>= n)
-// are treated as zero and never written, which is exact because the padded
-// factor is diag(L, I).
+// Blocked substitution in ONE launch per direction.  Workgroup w owns block
+// row i (forward: i = w; back: i = N-1-w) of up to KR right-hand sides:
+//   forward : r_i = b_i - sum_{p<i} L_ip y_p,   y_i = L_ii^{-1} r_i
+//   back    : r_i = y_i - sum_{p>i} L_pi^T x_p, x_i = L_ii^{-T} r_i
+// with the inverted diagonal blocks D_i = L_ii^{-T} computed once after the
+// factorisation (so the only sequential work per block row is two small
+// matrix-vector products).  Block rows are finished strictly in order, so
+// a single counter per right-hand-side chunk says how many are published:
+// the workgroup of block row i stores its result, fences (release, agent
+// scope) and sets the counter; a consumer polls it (acquire) before it reads
+// a published block.  Workgroups only wait on lower-numbered ones, which the
+// hardware dispatches first, so the chain always progresses; as a safety net
+// the wait is bounded: after spin_max polls the waiter raises the abort word,
+// every other waiter then stops waiting, and the aborted block rows are
+// written as NaN (never a hang, never a silently wrong number).
+//
+// Each tile a workgroup applies is loaded straight into registers before the
+// wait (its memory latency hides behind the wait), 512 threads.  With 16
+// right-hand sides (tile 128) both products run on the FP64 matrix cores
+// (see the use_mfma branch); otherwise on the vector ALUs:
+//   "N" product  out = M v    : thread (r = t mod B, g = t / B) holds
+//                               M(r, g*CPG .. g*CPG+CPG-1) (coalesced),
+//                               partial sums reduced over g through LDS;
+//   "T" product  out = M^T v  : thread (r = t / G, g = t mod G) holds
+//                               M(g*CPG .., r) (one contiguous run),
+//                               partial sums reduced over the G adjacent
+//                               lanes with shuffles.
+// forward: off-diagonal tiles N, diagonal D_i^T = T;  back: off-diagonal T,
+// diagonal D_i = N.  Padding rows (>= n) read as zero and are never written,
+// which is exact because the padded factor is diag(L, I).
 #include "internal.hpp"
 
 namespace chol {
 namespace {
 
-__device__ inline double readlane_f64(double v, int l) {
-  const uint64_t u = __builtin_bit_cast(uint64_t, v);
-  const int lo = __builtin_amdgcn_readlane((int)(uint32_t)u, l);
-  const int hi = __builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), l);
-  return __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
-}
+constexpr int NT = 512;  // threads per workgroup
 
-template <int B>
-struct Smem {
-  static constexpr int P = B + 1;          // LDS pitch of a staged tile (odd: conflict-free rows)
-  static constexpr int NC = 8;             // right-hand sides per pass of the tile product
-  static constexpr size_t tile_off = 0;
-  static constexpr size_t ys_off = tile_off + (size_t)B * P;
-  static constexpr size_t red_off = ys_off + (size_t)B * NC;
-  static constexpr size_t doubles = red_off + (size_t)256 * NC;
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+// 16 right-hand sides with tile 128 run on the FP64 matrix cores.
+template <int B, int KR> constexpr bool use_mfma() { return B == 128 && KR == 16; }
+
+template <int B, int KR> struct SolveSmem {
+  static constexpr int G = use_mfma<B, KR>() ? 1 : NT / B;
+  static constexpr int R = use_mfma<B, KR>() ? 1 : B * KR;
+  double v[B * KR];    // v[c * KR + j]: the vector block being applied
+  double own[B * KR];  // this block row's right-hand side, same layout
+  double red[G][R];    // partial sums of N products (VALU path)
 };
 
-// Copy a b x b column-major tile into LDS (pitch P), widening to FP64.  Each
-// thread keeps 8 independent 16-byte loads in flight before storing them.
-template <int B, typename T>
-__device__ inline void stage_tile(const T *__restrict__ src, double *dst) {
-  constexpr int P = Smem<B>::P;
-  constexpr int VE = 16 / sizeof(T);             // elements per 16-byte vector
-  constexpr int NVEC = B * B / VE / 256;         // vectors per thread
-  constexpr int BATCH = NVEC < 8 ? NVEC : 8;
-  const uint4 *s4 = reinterpret_cast<const uint4 *>(src);
-#pragma unroll
-  for (int b0 = 0; b0 < NVEC; b0 += BATCH) {
-    uint4 r[BATCH];
-#pragma unroll
-    for (int x = 0; x < BATCH; ++x) r[x] = s4[threadIdx.x + 256 * (b0 + x)];
-#pragma unroll
-    for (int x = 0; x < BATCH; ++x) {
-      const int e = (threadIdx.x + 256 * (b0 + x)) * VE;  // first element; same column
-      T v[VE];
-      __builtin_memcpy(v, &r[x], 16);
-      double *d = dst + (e / B) * P + (e % B);
-#pragma unroll
-      for (int y = 0; y < VE; ++y) d[y] = (double)v[y];
-    }
-  }
-}
-
-// out_i -= L_t y_src (TRANS = false) or out_i -= L_t^T y_src (TRANS = true)
-// with L_t staged in LDS; y_src and out are block rows of B.
-template <int B, int NCH, bool TRANS>
-__device__ void apply_tile(const double *lt, int64_t src_row0, int64_t dst_row0, double *B_,
-                           int64_t ldb, int64_t n, int64_t nrhs, double *ys, double *red) {
-  constexpr int H = 256 / B;  // threads per output row
-  constexpr int P = Smem<B>::P;
-  const int tid = threadIdx.x;
-  const int o = tid % B, h = tid / B;
-  for (int64_t c0 = 0; c0 < nrhs; c0 += NCH) {
-    const int nc = (int)min<int64_t>(NCH, nrhs - c0);
-    __syncthreads();
-    for (int e = tid; e < B * NCH; e += 256) {
-      const int m = e % B, cc = e / B;
-      const int64_t row = src_row0 + m;
-      ys[m * NCH + cc] = (cc < nc && row < n) ? B_[row + (c0 + cc) * ldb] : 0.0;
-    }
-    __syncthreads();
-    double acc[NCH];
-#pragma unroll
-    for (int cc = 0; cc < NCH; ++cc) acc[cc] = 0.0;
-#pragma unroll 8
-    for (int m = h; m < B; m += H) {
-      // forward: L[o][m];  back: L[m][o]
-      const double l = TRANS ? lt[o * P + m] : lt[m * P + o];
-#pragma unroll
-      for (int cc = 0; cc < NCH; ++cc) acc[cc] += l * ys[m * NCH + cc];
-    }
-#pragma unroll
-    for (int cc = 0; cc < NCH; ++cc) red[(h * B + o) * NCH + cc] = acc[cc];
-    __syncthreads();
-    if (h == 0) {
-      const int64_t row = dst_row0 + o;
-      if (row < n) {
-        for (int cc = 0; cc < nc; ++cc) {
-          double s = red[o * NCH + cc];
-          for (int hh = 1; hh < H; ++hh) s += red[(hh * B + o) * NCH + cc];
-          B_[row + (c0 + cc) * ldb] -= s;
+// Wait until *cnt >= need.  Thread 0 polls with relaxed agent-scope loads
+// (coherent, but without the cache invalidation an acquire implies, which
+// would disturb the tile streams of every workgroup on the XCD) and, once
+// the value is reached, issues one acquire fence; the barrier then orders
+// every thread's later reads after it.  `seen` caches the last value thread
+// 0 read, so blocks already known to be published cost no memory access.
+// Returns false when the wait was abandoned (abort raised here or elsewhere).
+__device__ bool wait_count(int *cnt, int *abort_word, int need, int spin_max, int &seen,
+                           int *ok_sh) {
+  if (threadIdx.x == 0) {
+    int good = 1;
+    if (seen < need) {
+      int it = 0;
+      for (;;) {
+        seen = __hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (seen >= need) break;
+        if (__hip_atomic_load(abort_word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 ||
+            ++it > spin_max) {
+          __hip_atomic_store(abort_word, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          good = 0;
+          break;
         }
+        __builtin_amdgcn_s_sleep(2);
       }
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
+    *ok_sh = good;
   }
+  __syncthreads();
+  return *ok_sh != 0;
 }
 
-// Diagonal solve with a column-major triangular block D staged in LDS:
-//   !UPPER (forward):  D = L_ss,   solve D y = b, rows ascending;
-//    UPPER (back):     D = L_ss^T, solve D x = y, rows descending.
-// Wave w handles right-hand sides w, w+4, ...; lane l owns rows l + 64 j.
-template <int B, bool UPPER>
-__device__ void diag_solve(const double *d, int64_t row0, double *B_, int64_t ldb, int64_t n,
-                           int64_t nrhs) {
-  constexpr int J = B / 64;
-  constexpr int P = Smem<B>::P;
-  constexpr int U = 8;  // steps per batch of column reads
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  double rinv[J];
-#pragma unroll
-  for (int j = 0; j < J; ++j) rinv[j] = 1.0 / d[(lane + 64 * j) * P + lane + 64 * j];
-  for (int64_t c = wave; c < nrhs; c += 4) {
-    double v[J];
-#pragma unroll
-    for (int j = 0; j < J; ++j) {
-      const int64_t row = row0 + lane + 64 * j;
-      v[j] = (row < n) ? B_[row + c * ldb] : 0.0;
-    }
-#pragma unroll
-    for (int jj = 0; jj < J; ++jj) {
-      const int jr = UPPER ? J - 1 - jj : jj;  // 64-row block holding the pivot rows
-      for (int b0 = 0; b0 < 64; b0 += U) {
-        double col[U][J];
-#pragma unroll
-        for (int q = 0; q < U; ++q) {
-          const int r = 64 * jr + (UPPER ? 63 - b0 - q : b0 + q);
-#pragma unroll
-          for (int j = 0; j < J; ++j) col[q][j] = d[r * P + lane + 64 * j];
-        }
-#pragma unroll
-        for (int q = 0; q < U; ++q) {
-          const int rl = UPPER ? 63 - b0 - q : b0 + q;  // lane holding row r
-          const int r = 64 * jr + rl;
-          const double xr = readlane_f64(v[jr], rl) * readlane_f64(rinv[jr], rl);
-#pragma unroll
-          for (int j = 0; j < J; ++j) {
-            const int m = lane + 64 * j;
-            if (m == r)
-              v[j] = xr;
-            else if (UPPER ? (m < r) : (m > r))
-              v[j] -= col[q][j] * xr;
-          }
-        }
-      }
-    }
-#pragma unroll
-    for (int j = 0; j < J; ++j) {
-      const int64_t row = row0 + lane + 64 * j;
-      if (row < n) B_[row + c * ldb] = v[j];
-    }
-  }
-}
-
-// FWD: workgroup w handles block row i = s + w using tile (i, s-1), and
-// workgroup 0 then solves L_ss.  BWD: block row i = s - w using tile
-// (s+1, i) transposed, and workgroup 0 then solves L_ss^T (from diag_t).
-template <int B, typename T, int NCH, bool FWD>
-__global__ __launch_bounds__(256) void trsv_step(const T *__restrict__ tiles,
-                                                 const T *__restrict__ diag_t, int64_t N,
-                                                 int64_t n, int64_t s, double *B_, int64_t ldb,
-                                                 int64_t nrhs) {
-  __shared__ double smem[Smem<B>::doubles];
-  double *lt = smem + Smem<B>::tile_off;
-  double *ys = smem + Smem<B>::ys_off;
-  double *red = smem + Smem<B>::red_off;
+template <int B, int KR, bool FWD, typename T>
+__global__ __launch_bounds__(NT) void solve_kernel(const T *__restrict__ tiles,
+                                                   const T *__restrict__ dinv, int64_t N,
+                                                   int64_t n, double *__restrict__ X, int64_t ldx,
+                                                   int64_t nrhs, int *__restrict__ counters,
+                                                   int *__restrict__ abort_word, int spin_max) {
+  constexpr int G = NT / B, CPG = B / G;
+  __shared__ SolveSmem<B, KR> sm;
+  __shared__ int ok_sh;
+  const int t = threadIdx.x;
+  const int ra = t % B, ga = t / B;  // N-product mapping
+  const int rb = t / G, gb = t % G;  // T-product mapping
   const int64_t w = blockIdx.x;
-  const bool has_update = FWD ? (s > 0) : (s < N - 1);
-  if (has_update) {
-    const int64_t i = FWD ? s + w : s - w;
-    const T *src = FWD ? tiles + tile_index(i, s - 1, N) * (int64_t)(B * B)
-                       : tiles + tile_index(s + 1, i, N) * (int64_t)(B * B);
-    stage_tile<B, T>(src, lt);
-    apply_tile<B, NCH, !FWD>(lt, FWD ? (s - 1) * B : (s + 1) * B, i * B, B_, ldb, n, nrhs, ys, red);
+  const int64_t i = FWD ? w : N - 1 - w;
+  const int64_t j0 = (int64_t)blockIdx.y * KR;
+  int *cnt = counters + blockIdx.y;
+  const int64_t BB = (int64_t)B * B;
+
+  auto load_n = [&](const T *M, double (&m)[CPG]) {
+#pragma unroll
+    for (int q = 0; q < CPG; ++q) m[q] = (double)M[(ga * CPG + q) * B + ra];
+  };
+  auto load_t = [&](const T *M, double (&m)[CPG]) {
+    const T *src = M + rb * B + gb * CPG;
+    constexpr int VE = 16 / sizeof(T);
+#pragma unroll
+    for (int q = 0; q < CPG; q += VE) {
+      T v[VE];
+      *(uint4 *)&v[0] = *(const uint4 *)(src + q);
+#pragma unroll
+      for (int e = 0; e < VE; ++e) m[q + e] = (double)v[e];
+    }
+  };
+  // block p of the solution (rows p*B + c) into sm.v, zero outside the matrix
+  auto load_v = [&](int64_t p) {
+    for (int e = t; e < B * KR; e += NT) {
+      const int c = e % B, j = e / B;
+      const int64_t row = p * B + c, col = j0 + j;
+      sm.v[c * KR + j] = (row < n && col < nrhs) ? X[col * ldx + row] : 0.0;
+    }
+  };
+  auto prod_n = [&](const double (&m)[CPG], double (&acc)[KR]) {
+#pragma unroll
+    for (int q = 0; q < CPG; ++q)
+#pragma unroll
+      for (int j = 0; j < KR; ++j) acc[j] += m[q] * sm.v[(ga * CPG + q) * KR + j];
+  };
+  auto prod_t = [&](const double (&m)[CPG], double (&acc)[KR]) {
+#pragma unroll
+    for (int q = 0; q < CPG; ++q)
+#pragma unroll
+      for (int j = 0; j < KR; ++j) acc[j] += m[q] * sm.v[(gb * CPG + q) * KR + j];
+  };
+  auto reduce_t = [&](double (&acc)[KR]) {  // over the G adjacent lanes of one row
+#pragma unroll
+    for (int j = 0; j < KR; ++j)
+#pragma unroll
+      for (int off = 1; off < G; off <<= 1) acc[j] += __shfl_xor(acc[j], off);
+  };
+  auto store = [&](int64_t r, int j, double v, bool good) {
+    const int64_t row = i * B + r, col = j0 + j;
+    if (row < n && col < nrhs) X[col * ldx + row] = good ? v : __builtin_nan("");
+  };
+
+  int seen = 0;
+  bool good = true;
+  // this block row's own right-hand side (forward b_i, back y_i), loaded up
+  // front so that its latency is off the critical path
+  for (int e = t; e < B * KR; e += NT) {
+    const int c = e % B, j = e / B;
+    const int64_t row = i * B + c, col = j0 + j;
+    sm.own[c * KR + j] = (row < n && col < nrhs) ? X[col * ldx + row] : 0.0;
   }
-  if (w == 0) {
-    __threadfence_block();
+  __syncthreads();
+
+  if constexpr (use_mfma<B, KR>()) {
+    // v_mfma_f64_16x16x4_f64, lane l = 16 g + q: A(row q, k g), B(k g, col q),
+    // result element e at (row g + 4e, col q).  Wave wv owns output rows
+    // 16 wv .. 16 wv + 15 (no reduction across waves); at k-step ks the lane
+    // uses tile index c = 32 g + ks for both operands, so its 32 A values of
+    // a transposed tile are one contiguous run.  B values are the 16 columns
+    // of the vector block, read from LDS (16 consecutive doubles per g).
+    const int lane = t & 63, wv = t >> 6, q = lane & 15, g = lane >> 4;
+    const int r0 = 16 * wv;
+    auto mload_n = [&](const T *M, double (&m)[32]) {  // A = M
+#pragma unroll
+      for (int ks = 0; ks < 32; ++ks) m[ks] = (double)M[(32 * g + ks) * B + r0 + q];
+    };
+    auto mload_t = [&](const T *M, double (&m)[32]) {  // A = M^T
+      const T *src = M + (r0 + q) * B + 32 * g;
+      constexpr int VE = 16 / sizeof(T);
+#pragma unroll
+      for (int ks = 0; ks < 32; ks += VE) {
+        T v[VE];
+        *(uint4 *)&v[0] = *(const uint4 *)(src + ks);
+#pragma unroll
+        for (int e = 0; e < VE; ++e) m[ks + e] = (double)v[e];
+      }
+    };
+    auto mprod = [&](const double (&m)[32], v4d &a) {
+#pragma unroll
+      for (int ks = 0; ks < 32; ++ks)
+        a = __builtin_amdgcn_mfma_f64_16x16x4f64(m[ks], sm.v[(32 * g + ks) * KR + q], a, 0, 0, 0);
+    };
+    double md[32], mm[32];
+    v4d a = {0.0, 0.0, 0.0, 0.0};
+    if (FWD) {
+      mload_t(dinv + i * BB, md);  // D_i^T
+      for (int64_t p = 0; p < i; ++p) {
+        mload_n(tiles + tile_index(i, p, N) * BB, mm);
+        good &= wait_count(cnt, abort_word, (int)(p + 1), spin_max, seen, &ok_sh);
+        load_v(p);
+        __syncthreads();
+        mprod(mm, a);
+        __syncthreads();
+      }
+    } else {
+      mload_n(dinv + i * BB, md);  // D_i
+      for (int64_t p = N - 1; p > i; --p) {
+        mload_t(tiles + tile_index(p, i, N) * BB, mm);
+        good &= wait_count(cnt, abort_word, (int)(N - p), spin_max, seen, &ok_sh);
+        load_v(p);
+        __syncthreads();
+        mprod(mm, a);
+        __syncthreads();
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int r = r0 + g + 4 * e;
+      sm.v[r * KR + q] = sm.own[r * KR + q] - a[e];
+    }
     __syncthreads();
-    const T *dsrc = FWD ? tiles + tile_index(s, s, N) * (int64_t)(B * B) : diag_t + s * (int64_t)(B * B);
-    stage_tile<B, T>(dsrc, lt);
+    v4d y = {0.0, 0.0, 0.0, 0.0};
+    mprod(md, y);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) store(r0 + g + 4 * e, q, y[e], good);
+  } else if (FWD) {
+    double dm[CPG], tm[CPG], acc[KR];
+#pragma unroll
+    for (int j = 0; j < KR; ++j) acc[j] = 0.0;
+    load_t(dinv + i * BB, dm);  // D_i^T product
+    for (int64_t p = 0; p < i; ++p) {
+      load_n(tiles + tile_index(i, p, N) * BB, tm);
+      good &= wait_count(cnt, abort_word, (int)(p + 1), spin_max, seen, &ok_sh);
+      load_v(p);
+      __syncthreads();
+      prod_n(tm, acc);
+      __syncthreads();
+    }
+    // r_i = b_i - sum over the column groups
+#pragma unroll
+    for (int j = 0; j < KR; ++j) sm.red[ga][ra * KR + j] = acc[j];
     __syncthreads();
-    diag_solve<B, !FWD>(lt, s * B, B_, ldb, n, nrhs);
+    if (t < B) {
+#pragma unroll
+      for (int j = 0; j < KR; ++j) {
+        double s = sm.red[0][t * KR + j];
+#pragma unroll
+        for (int g = 1; g < G; ++g) s += sm.red[g][t * KR + j];
+        sm.v[t * KR + j] = sm.own[t * KR + j] - s;
+      }
+    }
+    __syncthreads();
+    // y_i = D_i^T r_i
+    double y[KR];
+#pragma unroll
+    for (int j = 0; j < KR; ++j) y[j] = 0.0;
+    prod_t(dm, y);
+    reduce_t(y);
+    if (gb == 0) {
+#pragma unroll
+      for (int j = 0; j < KR; ++j) store(rb, j, y[j], good);
+    }
+  } else {
+    double dm[CPG], tm[CPG], acc[KR];
+#pragma unroll
+    for (int j = 0; j < KR; ++j) acc[j] = 0.0;
+    load_n(dinv + i * BB, dm);  // D_i product
+    for (int64_t p = N - 1; p > i; --p) {
+      load_t(tiles + tile_index(p, i, N) * BB, tm);
+      good &= wait_count(cnt, abort_word, (int)(N - p), spin_max, seen, &ok_sh);
+      load_v(p);
+      __syncthreads();
+      prod_t(tm, acc);
+      __syncthreads();
+    }
+    reduce_t(acc);
+    if (gb == 0) {
+#pragma unroll
+      for (int j = 0; j < KR; ++j) sm.v[rb * KR + j] = sm.own[rb * KR + j] - acc[j];
+    }
+    __syncthreads();
+    // x_i = D_i r_i
+    double x[KR];
+#pragma unroll
+    for (int j = 0; j < KR; ++j) x[j] = 0.0;
+    prod_n(dm, x);
+#pragma unroll
+    for (int j = 0; j < KR; ++j) sm.red[ga][ra * KR + j] = x[j];
+    __syncthreads();
+    if (t < B) {
+#pragma unroll
+      for (int j = 0; j < KR; ++j) {
+        double s = sm.red[0][t * KR + j];
+#pragma unroll
+        for (int g = 1; g < G; ++g) s += sm.red[g][t * KR + j];
+        store(t, j, s, good);
+      }
+    }
   }
+  // publish block row i
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  __syncthreads();
+  if (t == 0)
+    __hip_atomic_store(cnt, FWD ? (int)(i + 1) : (int)(N - i), __ATOMIC_RELEASE,
+                       __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__global__ void clear_i32_kernel(int *p, int count) {
+  for (int e = threadIdx.x; e < count; e += blockDim.x) p[e] = 0;
 }
 
 __global__ void scale_kernel(double *B_, int64_t n, int64_t ldb, int64_t nrhs, double alpha) {
@@ -205,62 +315,56 @@ __global__ void scale_kernel(double *B_, int64_t n, int64_t ldb, int64_t nrhs, d
   B_[r + c * ldb] *= alpha;
 }
 
-template <int B, typename T, int NCH>
-void trsv_run(const T *tiles, const T *diag_t, int64_t N, int64_t n, double *B_, int64_t ldb,
-              int64_t nrhs, bool fwd, hipStream_t st) {
-  const size_t sh = 0;  // all LDS is static (Smem<B>)
-  if (fwd) {
-    for (int64_t s = 0; s < N; ++s) {
-      const unsigned grid = (s == 0) ? 1u : (unsigned)(N - s);
-      hipLaunchKernelGGL((trsv_step<B, T, NCH, true>), dim3(grid), dim3(256), sh, st, tiles,
-                         diag_t, N, n, s, B_, ldb, nrhs);
-    }
-  } else {
-    for (int64_t s = N - 1; s >= 0; --s) {
-      const unsigned grid = (s == N - 1) ? 1u : (unsigned)(s + 1);
-      hipLaunchKernelGGL((trsv_step<B, T, NCH, false>), dim3(grid), dim3(256), sh, st, tiles,
-                         diag_t, N, n, s, B_, ldb, nrhs);
-    }
+template <int B, int KR, typename T>
+void solve_run(const T *tiles, const T *dinv, int64_t N, int64_t n, double *X, int64_t ldx,
+               int64_t nrhs, int *sync, int64_t sync_words, int spin_max, hipStream_t s) {
+  // sync = [abort, forward counters (nch), back counters (nch)]
+  const int64_t max_ch = (sync_words - 1) / 2;
+  for (int64_t c0 = 0; c0 < nrhs; c0 += max_ch * KR) {
+    const int64_t k = nrhs - c0 < max_ch * KR ? nrhs - c0 : max_ch * KR;
+    const int64_t nch = (k + KR - 1) / KR;
+    hipLaunchKernelGGL(clear_i32_kernel, dim3(1), dim3(256), 0, s, sync, (int)(1 + 2 * nch));
+    const dim3 grid((unsigned)N, (unsigned)nch);
+    double *Xc = X + c0 * ldx;
+    hipLaunchKernelGGL((solve_kernel<B, KR, true, T>), grid, dim3(NT), 0, s, tiles, dinv, N, n,
+                       Xc, ldx, k, sync + 1, sync, spin_max);
+    hipLaunchKernelGGL((solve_kernel<B, KR, false, T>), grid, dim3(NT), 0, s, tiles, dinv, N, n,
+                       Xc, ldx, k, sync + 1 + nch, sync, spin_max);
   }
 }
 
 template <int B, typename T>
-void trsv_rhs(const T *tiles, const T *dt, int64_t N, int64_t n, double *B_, int64_t ldb,
-              int64_t nrhs, bool fwd, hipStream_t st) {
+void solve_rhs(const T *tiles, const T *dinv, int64_t N, int64_t n, double *X, int64_t ldx,
+               int64_t nrhs, int *sync, int64_t sync_words, int spin_max, hipStream_t s) {
   if (nrhs == 1)
-    trsv_run<B, T, 1>(tiles, dt, N, n, B_, ldb, nrhs, fwd, st);
+    solve_run<B, 1, T>(tiles, dinv, N, n, X, ldx, nrhs, sync, sync_words, spin_max, s);
+  else if (nrhs <= 4)
+    solve_run<B, 4, T>(tiles, dinv, N, n, X, ldx, nrhs, sync, sync_words, spin_max, s);
   else
-    trsv_run<B, T, 8>(tiles, dt, N, n, B_, ldb, nrhs, fwd, st);
-}
-
-void trsv_dispatch(const void *tiles, const void *dt, int store, int b, int64_t N, int64_t n,
-                   double *B_, int64_t ldb, int64_t nrhs, bool fwd, hipStream_t st) {
-  if (N <= 0 || nrhs <= 0) return;
-  if (b == 128) {
-    if (store == STORE_F64)
-      trsv_rhs<128, double>((const double *)tiles, (const double *)dt, N, n, B_, ldb, nrhs, fwd,
-                            st);
-    else
-      trsv_rhs<128, float>((const float *)tiles, (const float *)dt, N, n, B_, ldb, nrhs, fwd, st);
-  } else {
-    if (store == STORE_F64)
-      trsv_rhs<64, double>((const double *)tiles, (const double *)dt, N, n, B_, ldb, nrhs, fwd,
-                           st);
-    else
-      trsv_rhs<64, float>((const float *)tiles, (const float *)dt, N, n, B_, ldb, nrhs, fwd, st);
-  }
+    solve_run<B, 16, T>(tiles, dinv, N, n, X, ldx, nrhs, sync, sync_words, spin_max, s);
 }
 
 }  // namespace
 
-void launch_trsv_fwd(const void *tiles, const void *diag_t, int store, int b, int64_t N,
-                     int64_t n, double *B_, int64_t ldb, int64_t nrhs, hipStream_t s) {
-  trsv_dispatch(tiles, diag_t, store, b, N, n, B_, ldb, nrhs, true, s);
-}
-
-void launch_trsv_bwd(const void *tiles, const void *diag_t, int store, int b, int64_t N,
-                     int64_t n, double *B_, int64_t ldb, int64_t nrhs, hipStream_t s) {
-  trsv_dispatch(tiles, diag_t, store, b, N, n, B_, ldb, nrhs, false, s);
+void launch_solve(const void *tiles, const void *dinv, int store, int b, int64_t N, int64_t n,
+                  double *X, int64_t ldx, int64_t nrhs, int *sync, int64_t sync_words,
+                  int spin_max, hipStream_t s) {
+  if (N <= 0 || nrhs <= 0 || sync_words < 3) return;
+  if (b == 128) {
+    if (store == STORE_F64)
+      solve_rhs<128, double>((const double *)tiles, (const double *)dinv, N, n, X, ldx, nrhs,
+                             sync, sync_words, spin_max, s);
+    else
+      solve_rhs<128, float>((const float *)tiles, (const float *)dinv, N, n, X, ldx, nrhs, sync,
+                            sync_words, spin_max, s);
+  } else {
+    if (store == STORE_F64)
+      solve_rhs<64, double>((const double *)tiles, (const double *)dinv, N, n, X, ldx, nrhs,
+                            sync, sync_words, spin_max, s);
+    else
+      solve_rhs<64, float>((const float *)tiles, (const float *)dinv, N, n, X, ldx, nrhs, sync,
+                           sync_words, spin_max, s);
+  }
 }
 
 void launch_scale(double *B_, int64_t n, int64_t ldb, int64_t nrhs, double alpha, hipStream_t s) {

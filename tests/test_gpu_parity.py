@@ -247,6 +247,50 @@ def test_fp64_refine_converges_immediately():
     assert res.converged and res.iters == 0
 
 
+@pytest.mark.parametrize("n,tile,k", [(1000, 128, 1), (1000, 128, 3), (1000, 128, 37),
+                                      (300, 64, 5), (130, 128, 2), (2000, 128, 16)])
+def test_solve_shapes_parity(n, tile, k):
+    # ragged last tile, every right-hand-side chunk width (1, 4, 16 and a
+    # partial chunk), both tile sizes
+    X, B = gp_inputs.gp_problem(n, seed=5, k=k)
+    A = oracle.gp_assemble(X, 1.0, 1.0, 0.1)
+    Lref, _ = oracle.cholesky(A)
+    xref = oracle.solve(Lref, B)
+    F = P.chol_factor(dev(A), "fp64", tile)
+    Bd = dev(B)
+    P.chol_solve(F, Bd)
+    x = host(Bd)
+    for c in range(k):
+        err = np.linalg.norm(x[:, c] - xref[:, c]) / np.linalg.norm(xref[:, c])
+        assert err <= 1e-10, (c, err)
+
+
+def test_solve_bounded_wait_never_hangs():
+    # With a one-poll bound the inter-workgroup waits give up almost at once:
+    # the solve must still finish, and every row is either right or NaN.
+    # Afterwards (default bound) the same solve is exact again.
+    n = 2048
+    X, B = gp_inputs.gp_problem(n, seed=6, k=2)
+    A = oracle.gp_assemble(X, 1.0, 1.0, 0.1)
+    xref = oracle.solve(oracle.cholesky(A)[0], B)
+    F = P.chol_factor(dev(A), "fp64", 128)
+    old = P.get_option("solve_spin_max")
+    try:
+        P.set_option("solve_spin_max", 1)
+        Bd = dev(B)
+        P.chol_solve(F, Bd)
+        x = host(Bd)
+    finally:
+        P.set_option("solve_spin_max", old)
+    ok = np.isnan(x) | (np.abs(x - xref) <= 1e-8 * np.abs(xref).max())
+    assert ok.all()
+    Bd = dev(B)
+    P.chol_solve(F, Bd)
+    x = host(Bd)
+    assert np.isfinite(x).all()
+    assert np.linalg.norm(x - xref) / np.linalg.norm(xref) <= 1e-10
+
+
 # ----------------------------------------------------------- edge cases ---
 
 def test_empty_and_tiny():
