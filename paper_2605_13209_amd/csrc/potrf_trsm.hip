@@ -15,192 +15,287 @@ namespace chol {
 namespace {
 
 // ---------------------------------------------------------------- Step 1 --
-// One workgroup of 256 threads factors a B x B diagonal tile (B = 16 M) held
-// in registers as FP64.  Threads form a 16 x 16 grid; thread (tr, tc) owns
-// the elements (tr + 16 m, tc + 16 n), m, n < M (a cyclic distribution, so the
-// shrinking trailing triangle stays spread over all threads).  Right-looking,
-// one column k per step:
-//   (1) the owner of (k, k) publishes the pivot;            barrier
-//   (2) everyone checks it (uniform exit on failure); the owners of column k
-//       scale it by 1/sqrt(pivot) and publish it;          barrier
-//   (3) every thread applies the rank-1 update to its trailing elements.
-// Register indices are compile-time: the column loop is split into an
-// unrolled block index km and a runtime offset kr (k = 16 km + kr), and the
-// blocks that are inactive at block km are skipped at compile time.  The tile
-// is moved between HBM and registers through LDS, half a tile at a time (so
-// the kernel's LDS fits next to a trailing-update workgroup on one CU), with
-// contiguous global accesses.
+__device__ inline double readlane_f64(double v, int l) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, v);
+  const int lo = __builtin_amdgcn_readlane((int)(uint32_t)u, l);
+  const int hi = __builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), l);
+  return __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+
+// One workgroup of 256 threads factors a B x B diagonal tile in FP64,
+// blocked by 16 columns (right-looking).  The trailing part of the tile lives
+// in registers: threads form a 16 x 16 grid and thread (tr, tc) owns the
+// elements (tr + 16 m, tc + 16 n) of the trailing submatrix, m, n < B/16 --
+// one element of every 16 x 16 block.  For each block column:
+//   (1) the diagonal block goes to LDS (one element per thread);      barrier
+//   (2) one wave factors it, lane l holding row l: per column the pivot
+//       comes by readlane and the scaled column goes through LDS to the
+//       wave (in-order LDS within a wave, no barrier);                 barrier
+//   (3) the panel below goes to LDS;                                   barrier
+//       one thread per panel row solves X L_kk^T = P by substitution
+//       (multiplying by the reciprocal diagonal);                      barrier
+//   (4) every thread applies the rank-16 update to its trailing elements,
+//       and the finished 16 columns go from LDS to HBM;                 barrier
+//   (5) the registers shift by one block, so the next diagonal block is
+//       again at register index 0 (all register indices stay compile-time
+//       while the block loop itself is not unrolled).
+// So a tile costs 5 barriers per 16 columns instead of 2 per column.  A
+// failed pivot is reported by the wave of step (2) and every thread leaves
+// after the barrier.  The tile is loaded through LDS a quarter at a time
+// (contiguous global reads).  256 threads, LDS below 36 KB: the kernel fits
+// on a CU beside one trailing-update workgroup.
 template <int B, typename T>
 __global__ __launch_bounds__(256) void potrf_kernel(T *__restrict__ tiles, int64_t N, int64_t c,
                                                     int64_t *__restrict__ info) {
   if (*info != 0) return;
   constexpr int M = B / 16;
+  constexpr int NB = 16;
+  constexpr int PP = NB + 2;  // pitch of the diagonal block and the panel (16-byte rows)
+  constexpr int QC = 32;      // columns per staging quarter
   constexpr int LD = B + 1;
-  constexpr int HC = B / 2;  // columns staged per half
-  __shared__ double stage[HC * LD];
-  __shared__ double col[B];
-  __shared__ double piv;
+  constexpr int WORK = NB * PP + (B - NB) * PP + 2 * NB;
+  constexpr int SMEM = (QC * LD > WORK) ? QC * LD : WORK;
+  __shared__ __attribute__((aligned(16))) double sm[SMEM];
+  __shared__ int fail;
+  double *stage = sm;               // QC x LD, while loading
+  double *dg = sm;                  // NB x PP diagonal block
+  double *pn = sm + NB * PP;        // (B - NB) x PP panel below it
+  double *cb = pn + (B - NB) * PP;  // column broadcast of step (2)
+  double *rd = cb + NB;             // reciprocal diagonal of the block
   T *tile = tiles + tile_index(c, c, N) * (int64_t)(B * B);
   const int t = threadIdx.x, tc = t & 15, tr = t >> 4;
+  if (t == 0) fail = 0;
   double a[M][M];
 #pragma unroll
-  for (int hf = 0; hf < 2; ++hf) {
-    for (int e = t; e < HC * B; e += 256) {
+  for (int q4 = 0; q4 < B / QC; ++q4) {
+    for (int e = t; e < QC * B; e += 256) {
       const int r = e % B, cc = e / B;
-      stage[cc * LD + r] = (double)tile[(hf * HC + cc) * B + r];
+      stage[cc * LD + r] = (double)tile[(q4 * QC + cc) * B + r];
     }
     __syncthreads();
 #pragma unroll
     for (int m = 0; m < M; ++m)
 #pragma unroll
-      for (int n = hf * M / 2; n < (hf + 1) * M / 2; ++n)
-        a[m][n] = stage[(tc + 16 * n - hf * HC) * LD + tr + 16 * m];
+      for (int nn = 0; nn < 2; ++nn)
+        a[m][2 * q4 + nn] = stage[(tc + 16 * nn) * LD + tr + 16 * m];
     __syncthreads();
   }
 
+#pragma unroll 1
+  for (int kb = 0; kb < M; ++kb) {
+    const int rem = M - kb;  // register blocks still trailing
+    // (1) diagonal block to LDS
+    dg[tr * PP + tc] = a[0][0];
+    __syncthreads();
+    // (2) one wave factors it
+    if (t < 64) {
+      const int l = t;
+      double x[NB];
 #pragma unroll
-  for (int km = 0; km < M; ++km) {
-    for (int kr = 0; kr < 16; ++kr) {
-      const int k = 16 * km + kr;
-      if (tr == kr && tc == kr) piv = a[km][km];
-      __syncthreads();
-      const double d = piv;
-      if (!(d > 0.0)) {  // uniform: every thread read the same pivot
-        if (t == 0) *info = c * B + k + 1;
-        return;
+      for (int j = 0; j < NB; ++j) x[j] = (l < NB) ? dg[l * PP + j] : 0.0;
+      int bad = 0;  // first failed pivot (1-based); uniform across the wave
+#pragma unroll
+      for (int k = 0; k < NB; ++k) {
+        double d = readlane_f64(x[k], k);
+        if (!(d > 0.0)) {
+          if (!bad) bad = k + 1;
+          d = 1.0;  // keep going without NaNs; the result is discarded
+        }
+        const double lkk = sqrt(d);
+        const double rl = 1.0 / lkk;
+        x[k] = (l == k) ? lkk : (l > k ? x[k] * rl : x[k]);
+        if (l == k) rd[k] = rl;
+        if (l < NB) cb[l] = x[k];
+#pragma unroll
+        for (int j = k + 1; j < NB; ++j) x[j] -= x[k] * cb[j];
+        __builtin_amdgcn_sched_barrier(0);
       }
-      const double lkk = sqrt(d);
-      const double rl = 1.0 / lkk;  // the column is scaled by the reciprocal
-      if (tc == kr) {
+      if (bad) {
+        if (l == 0) {
+          *info = c * B + kb * NB + bad;
+          fail = 1;
+        }
+      } else if (l < NB) {
 #pragma unroll
-        for (int m = km; m < M; ++m) {
-          const int i = tr + 16 * m;
-          if (i > k) {
-            a[m][km] = a[m][km] * rl;
-            col[i] = a[m][km];
-          } else if (i == k) {
-            a[m][km] = lkk;
+        for (int j = 0; j < NB; ++j) dg[l * PP + j] = x[j];
+      }
+    }
+    __syncthreads();
+    if (fail) return;  // uniform
+    if (kb + 1 < M) {
+      // (3) panel below to LDS, solved row by row
+      const int PR = B - NB * (kb + 1);
+#pragma unroll
+      for (int m = 1; m < M; ++m)
+        if (m < rem) pn[(tr + 16 * (m - 1)) * PP + tc] = a[m][0];
+      __syncthreads();
+      if (t < PR) {
+        double x[NB];
+#pragma unroll
+        for (int j = 0; j < NB; j += 2) *(double2 *)&x[j] = *(const double2 *)&pn[t * PP + j];
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+          double s = x[j];
+#pragma unroll
+          for (int i = 0; i < j; ++i) s -= x[i] * dg[j * PP + i];
+          x[j] = s * rd[j];
+          __builtin_amdgcn_sched_barrier(0);
+        }
+#pragma unroll
+        for (int j = 0; j < NB; j += 2) *(double2 *)&pn[t * PP + j] = *(const double2 *)&x[j];
+      }
+      __syncthreads();
+      // (4) rank-16 update of the trailing elements (blocks m >= n >= 1)
+#pragma unroll
+      for (int k = 0; k < NB; k += 2) {
+        double2 pr[M], pc[M];
+#pragma unroll
+        for (int m = 1; m < M; ++m) {
+          pr[m] = *(const double2 *)&pn[(tr + 16 * (m - 1)) * PP + k];
+          pc[m] = *(const double2 *)&pn[(tc + 16 * (m - 1)) * PP + k];
+        }
+#pragma unroll
+        for (int m = 1; m < M; ++m)
+          if (m < rem) {
+#pragma unroll
+            for (int n = 1; n <= m; ++n) {
+              a[m][n] -= pr[m].x * pc[n].x;
+              a[m][n] -= pr[m].y * pc[n].y;
+            }
           }
-        }
-      }
-      __syncthreads();
-      double ci[M], cj[M];
-#pragma unroll
-      for (int m = km; m < M; ++m) {
-        ci[m] = col[tr + 16 * m];
-        cj[m] = col[tc + 16 * m];
-      }
-#pragma unroll
-      for (int m = km; m < M; ++m) {
-#pragma unroll
-        for (int n = km; n <= m; ++n) {
-          const int i = tr + 16 * m, j = tc + 16 * n;
-          if (j > k && i >= j) a[m][n] -= ci[m] * cj[n];
-        }
+        __builtin_amdgcn_sched_barrier(0);
       }
     }
-  }
-#pragma unroll
-  for (int hf = 0; hf < 2; ++hf) {
-    __syncthreads();
-#pragma unroll
-    for (int m = 0; m < M; ++m)
-#pragma unroll
-      for (int n = hf * M / 2; n < (hf + 1) * M / 2; ++n) {
-        const int i = tr + 16 * m, j = tc + 16 * n;
-        stage[(j - hf * HC) * LD + i] = (i >= j) ? a[m][n] : 0.0;
-      }
-    __syncthreads();
-    for (int e = t; e < HC * B; e += 256) {
-      const int r = e % B, cc = e / B;
-      tile[(hf * HC + cc) * B + r] = (T)stage[cc * LD + r];
+    // the finished 16 columns (zero above the diagonal) from LDS to HBM
+    const int j0 = NB * kb;
+    for (int e = t; e < NB * B; e += 256) {
+      const int r = e % B, jj = e / B, j = j0 + jj;
+      double v = 0.0;
+      if (r >= j) v = (r < j0 + NB) ? dg[(r - j0) * PP + jj] : pn[(r - j0 - NB) * PP + jj];
+      tile[(int64_t)j * B + r] = (T)v;
     }
+    __syncthreads();
+    // (5) shift: the next diagonal block moves to register index 0
+#pragma unroll
+    for (int m = 0; m + 1 < M; ++m)
+#pragma unroll
+      for (int n = 0; n + 1 < M; ++n) a[m][n] = a[m + 1][n + 1];
   }
 }
 
 // ---------------------------------------------------------------- Step 2 --
-// X L^T = A for every tile (i, c), i in [c+1, N): each row of X is an
-// independent forward substitution with L = L_cc.  One workgroup of 256
-// threads per tile; thread (r, h) handles row r (r = t mod B) and owns the
-// column blocks q (16 columns each) with q mod H = h (H = 256 / B), keeping
-// its solved values in registers.  For block q:
-//   the 16-row strip of L needed (rows 16q.., columns < 16q + 16) sits in
-//   LDS and is read as broadcasts; the strip of block q+1 is loaded into
-//   registers while block q computes (double-buffered strips);
-//   every thread sums x_m L[16q+u][m] over its own earlier blocks;
-//   the owner of block q adds the H partial sums (in a fixed order) to the
-//   right-hand side and solves the 16 x 16 triangle by substitution,
-//   multiplying by reciprocals of the diagonal.
-// IDENT: the right-hand side is the identity (X is only written), which gives
-// X = L^{-T}: used for the inverted diagonal blocks of the solves.
+// X L^T = A for a tile, L = L_cc: each row of X is an independent forward
+// substitution.  One workgroup of 256 threads per tile, blocked by 16
+// columns.  Column block q of L (rows 16q .. B-1, 16 columns) is staged in
+// LDS (pitch 18, double-buffered: block q+1 is loaded into registers while
+// block q is processed), with the reciprocal diagonal of L.  The unsolved
+// part of the tile lives in registers, thread (tr, tc) owning elements
+// (tr + 16 m, tc + 16 n).  For each column block:
+//   (1) the owners copy the block of X to LDS;                        barrier
+//   (2) one thread per row solves its 16 values against the 16 x 16
+//       diagonal block of L by substitution;                           barrier
+//   (3) the solved block goes to HBM and every thread subtracts its
+//       product with the block's part of L from its remaining columns;
+//                                                                      barrier
+//   (4) the registers shift by one block column (compile-time indices
+//       while the block loop is not unrolled).
+// IDENT: the right-hand side is the identity (X is only written), which
+// gives X = L^{-T}: the inverted diagonal blocks of the solves.
 template <int B, typename T, bool IDENT>
 __device__ __forceinline__ void trsm_tile(const T *__restrict__ L, T *__restrict__ X) {
-  constexpr int CB = 16, NB = B / CB, H = 256 / B;
-  __shared__ double ls[2][B * CB];         // ls[.][m * CB + u] = L[16q + u][m]
-  __shared__ double part[H][CB][B + 1];    // partial sums per (h, u, row)
-  const int t = threadIdx.x, r = t % B, h = t / B;
-  // strip q: elements e < (q + 1) * CB * CB, e = m * CB + u -> L[m * B + 16q + u]
-  for (int e = t; e < CB * CB; e += 256) ls[0][e] = (double)L[(e / CB) * B + (e % CB)];
-  __syncthreads();
-  double x[NB / H][CB];
+  constexpr int M = B / 16, NB = 16, PP = NB + 2;
+  constexpr int PF = (B * NB + 255) / 256;                  // prefetched L values per thread
+  __shared__ __attribute__((aligned(16))) double ls[2][B * PP];  // L column blocks
+  __shared__ __attribute__((aligned(16))) double px[B * PP];     // current block of X
+  __shared__ double rdl[B];                                      // 1 / L_jj
+  const int t = threadIdx.x, tc = t & 15, tr = t >> 4;
+  // column block q of L: element (16 q + r, 16 q + u), r < B - 16 q, u < 16
+  auto lget = [&](int q, double (&v)[PF]) {
+    const int rows = B - 16 * q;
 #pragma unroll
-  for (int q = 0; q < NB; ++q) {
-    const double *lq = ls[q & 1];
-    // prefetch the next strip into registers
-    constexpr int MAXP = (NB + 1) * CB * CB / 256 + 1;
-    double nxt[MAXP];
-    if (q + 1 < NB) {
-#pragma unroll
-      for (int x2 = 0; x2 < MAXP; ++x2) {
-        const int e = t + 256 * x2;
-        if (e < (q + 2) * CB * CB) nxt[x2] = (double)L[(e / CB) * B + (q + 1) * CB + (e % CB)];
-      }
+    for (int x = 0; x < PF; ++x) {
+      const int e = t + 256 * x, r = e % rows, u = e / rows;
+      v[x] = (e < rows * NB) ? (double)L[(int64_t)(16 * q + u) * B + 16 * q + r] : 0.0;
     }
-    double acc[CB];
+  };
+  auto lput = [&](int q, const double (&v)[PF]) {
+    const int rows = B - 16 * q;
 #pragma unroll
-    for (int u = 0; u < CB; ++u) acc[u] = 0.0;
+    for (int x = 0; x < PF; ++x) {
+      const int e = t + 256 * x, r = e % rows, u = e / rows;
+      if (e < rows * NB) ls[q & 1][r * PP + u] = v[x];
+    }
+  };
+  {
+    double v[PF];
+    lget(0, v);
+    lput(0, v);
+  }
+  for (int e = t; e < B; e += 256) rdl[e] = 1.0 / (double)L[(int64_t)e * B + e];
+  double a[M][M];
 #pragma unroll
-    for (int qq = 0; qq < q; ++qq) {
-      if (qq % H == h) {
+  for (int m = 0; m < M; ++m)
 #pragma unroll
-        for (int mm = 0; mm < CB; ++mm) {
-          const double xm = x[qq / H][mm];
+    for (int n = 0; n < M; ++n) {
+      const int r = tr + 16 * m, cc = tc + 16 * n;
+      a[m][n] = IDENT ? (r == cc ? 1.0 : 0.0) : (double)X[(int64_t)cc * B + r];
+    }
+#pragma unroll 1
+  for (int q = 0; q < M; ++q) {
+    const double *lq = ls[q & 1];  // rows 16q.. of L, pitch PP
+    double nxt[PF];
+    if (q + 1 < M) lget(q + 1, nxt);
+    // (1) block q of X to LDS
 #pragma unroll
-          for (int u = 0; u < CB; ++u) acc[u] += xm * lq[(qq * CB + mm) * CB + u];
+    for (int m = 0; m < M; ++m) px[(tr + 16 * m) * PP + tc] = a[m][0];
+    __syncthreads();
+    // (2) one thread per row: x L_qq^T = rhs
+    if (t < B) {
+      double x[NB];
+#pragma unroll
+      for (int j = 0; j < NB; j += 2) *(double2 *)&x[j] = *(const double2 *)&px[t * PP + j];
+#pragma unroll
+      for (int j = 0; j < NB; ++j) {
+        double sacc = x[j];
+#pragma unroll
+        for (int i = 0; i < j; ++i) sacc -= x[i] * lq[j * PP + i];
+        x[j] = sacc * rdl[16 * q + j];
+        __builtin_amdgcn_sched_barrier(0);
+      }
+#pragma unroll
+      for (int j = 0; j < NB; j += 2) *(double2 *)&px[t * PP + j] = *(const double2 *)&x[j];
+    }
+    __syncthreads();
+    // (3) the solved block to HBM; update of the remaining columns
+    for (int e = t; e < B * NB; e += 256) {
+      const int r = e % B, u = e / B;
+      X[(int64_t)(16 * q + u) * B + r] = (T)px[r * PP + u];
+    }
+#pragma unroll
+    for (int k = 0; k < NB; k += 2) {
+      double2 xr[M], lc[M];
+#pragma unroll
+      for (int m = 0; m < M; ++m) xr[m] = *(const double2 *)&px[(tr + 16 * m) * PP + k];
+#pragma unroll
+      for (int n = 1; n < M; ++n) lc[n] = *(const double2 *)&lq[(tc + 16 * n) * PP + k];
+#pragma unroll
+      for (int n = 1; n < M; ++n)
+        if (n < M - q) {
+#pragma unroll
+          for (int m = 0; m < M; ++m) {
+            a[m][n] -= xr[m].x * lc[n].x;
+            a[m][n] -= xr[m].y * lc[n].y;
+          }
         }
-      }
+      __builtin_amdgcn_sched_barrier(0);
     }
-#pragma unroll
-    for (int u = 0; u < CB; ++u) part[h][u][r] = acc[u];
+    if (q + 1 < M) lput(q + 1, nxt);  // the other buffer: last read in block q-1
     __syncthreads();
-    if (h == q % H) {
-      double v[CB], rd[CB];
+    // (4) shift: the next block column moves to register index 0
 #pragma unroll
-      for (int u = 0; u < CB; ++u) {
-        rd[u] = 1.0 / lq[(q * CB + u) * CB + u];
-        double s = part[0][u][r];
+    for (int m = 0; m < M; ++m)
 #pragma unroll
-        for (int hh = 1; hh < H; ++hh) s += part[hh][u][r];
-        const double rhs = IDENT ? (q * CB + u == r ? 1.0 : 0.0) : (double)X[(q * CB + u) * B + r];
-        v[u] = rhs - s;
-      }
-#pragma unroll
-      for (int u = 0; u < CB; ++u) {
-#pragma unroll
-        for (int w = 0; w < u; ++w) v[u] -= v[w] * lq[(q * CB + w) * CB + u];
-        v[u] = v[u] * rd[u];
-        x[q / H][u] = v[u];
-        X[(q * CB + u) * B + r] = (T)v[u];
-      }
-    }
-    if (q + 1 < NB) {
-#pragma unroll
-      for (int x2 = 0; x2 < MAXP; ++x2) {
-        const int e = t + 256 * x2;
-        if (e < (q + 2) * CB * CB) ls[(q + 1) & 1][e] = nxt[x2];
-      }
-    }
-    __syncthreads();
+      for (int n = 0; n + 1 < M; ++n) a[m][n] = a[m][n + 1];
   }
 }
 
