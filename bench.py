@@ -36,6 +36,17 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+# Bytes moved between L2 and the memory fabric per launch of the bulk FP64
+# update (update_f64_kernel<0>) in the n = 32768 workload: two rocprofv3 --pmc
+# runs (FETCH_SIZE, WRITE_SIZE) over one factorisation, each scaled by what
+# the same counter reads for a plain 1 GiB copy (FETCH_SIZE x 2.0, WRITE_SIZE
+# x 1.0).  Valid only for the kernel source it was measured on; otherwise
+# reported as null.  Algorithmic bytes per launch (each C tile read and
+# written once, each panel tile read once): 2.835e9.
+TRAFFIC = {"update_hip_sha256_16": "1e405aab669cd4df", "n": 32768, "bytes_per_launch": 5.494e9,
+           "algorithmic_bytes_per_launch": 2.835e9,
+           "source": "profiles/update_f64_kernel_traffic_n32768.md"}
+
 METRIC = "Cholesky GFLOP/s (n^3/3) + time-to-1e-10 solve, FP64 vs mixed; p50/p99 latency"
 FP64_PEAK_TFLOPS = 78.6   # MI355X dense FP64 matrix peak
 FP32_PEAK_TFLOPS = 157.3  # MI355X dense FP32 matrix peak
@@ -82,10 +93,13 @@ def main():
     ap.add_argument("--cpu-n", type=int, default=8192)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
+    ap.add_argument("--copy-probe-gib", type=float, default=0.0,
+                    help="before the workload, one plain device copy of this many GiB (outside the "
+                         "timed region): the known-size kernel that calibrates byte counters")
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
+        print(json.dumps({"error": "the solver runs on one GPU; --gpus must be 1 "
                                    "(multi-GPU sharding is a design note, not implemented)"}))
         sys.exit(2)
 
@@ -97,6 +111,12 @@ def main():
         print(json.dumps({"error": "no GPU visible"}))
         sys.exit(1)
     torch.cuda.set_device(0)
+    if args.copy_probe_gib > 0:
+        src = torch.ones(int(args.copy_probe_gib * (1 << 27)), dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     if args.panel_width:
         P.set_option("panel_width", args.panel_width)
     if args.lookahead >= 0:
@@ -145,7 +165,7 @@ def main():
         for _ in range(warmup):
             F = step()
         torch.cuda.synchronize()
-        if F.info() != 0:
+        if warmup and F.info() != 0:
             raise RuntimeError(f"factorisation failed, info={F.info()}")
         P.chol_profile_reset()
         if not args.no_profile:
@@ -239,7 +259,10 @@ def main():
     if kl > 0 and kms > 0:
         ach = kfl / (kms * 1e-3) / 1e12
         roofline = {"bound": "mfma", "achieved": round(ach, 3), "peak": peak, "unit": "TFLOP/s",
-                    "frac": round(ach / peak, 4), "traffic": None,
+                    "frac": round(ach / peak, 4), "traffic": measured_traffic(n, dtype),
+                    "traffic_unit": "bytes per launch between L2 and the memory fabric (calibrated counters)",
+                    "algorithmic_bytes_per_launch": TRAFFIC["algorithmic_bytes_per_launch"]
+                    if measured_traffic(n, dtype) else None,
                     "kernel": ("update_f64_kernel<0>" if dtype == "f64" else "update_f32_kernel<0>")
                     + " (Step-3 update of the trailing triangle)", "launches": kl,
                     "avg_launch_us": round(kms * 1e3 / kl, 2),
@@ -253,6 +276,20 @@ def main():
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_n)
     print(json.dumps(out), flush=True)
+
+
+def measured_traffic(n: int, dtype: str):
+    """Counter-measured bytes per launch of the bulk update, or None when the
+    workload or the kernel source differs from the one the counters saw."""
+    import hashlib
+    src = os.path.join(ROOT, "paper_2605_13209_amd", "csrc", "update.hip")
+    try:
+        h = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    except OSError:
+        return None
+    if dtype != "f64" or n != TRAFFIC["n"] or h != TRAFFIC["update_hip_sha256_16"]:
+        return None
+    return TRAFFIC["bytes_per_launch"]
 
 
 def bench_serve(args):
