@@ -50,6 +50,7 @@ TRAFFIC = {"update_hip_sha256_16": "1e405aab669cd4df", "n": 32768, "bytes_per_la
 METRIC = "Cholesky GFLOP/s (n^3/3) + time-to-1e-10 solve, FP64 vs mixed; p50/p99 latency"
 FP64_PEAK_TFLOPS = 78.6   # MI355X dense FP64 matrix peak
 FP32_PEAK_TFLOPS = 157.3  # MI355X dense FP32 matrix peak
+FP16_PEAK_TFLOPS = 2500.0  # MI355X dense FP16 matrix peak
 HP = (1.0, 1.0, 0.1)      # lengthscale, variance, noise
 
 
@@ -81,7 +82,8 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="fp64_n32768",
-                    choices=["fp64_n32768", "fp64_n1024", "fp64_n65536", "mixed_n65536", "serve"])
+                    choices=["fp64_n32768", "fp64_n1024", "fp64_n65536", "mixed_n65536",
+                             "mixed_fp16_n131072", "serve"])
     ap.add_argument("--duration", type=float, default=10.0, help="serve: seconds of arrivals")
     ap.add_argument("--rate", type=float, default=200.0, help="serve: mean arrivals per second")
     ap.add_argument("--workers", type=int, default=8, help="serve: concurrent requests")
@@ -127,6 +129,8 @@ def main():
     wl = args.workload
     if wl == "serve":
         return bench_serve(args)
+    if wl == "mixed_fp16_n131072":
+        return bench_fp16(args)
     n = args.n or {"fp64_n32768": 32768, "fp64_n1024": 1024, "fp64_n65536": 65536, "mixed_n65536": 65536}[wl]
     tile = args.tile
     steps, warmup = args.steps, args.warmup
@@ -276,6 +280,77 @@ def main():
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_n)
     print(json.dumps(out), flush=True)
+
+
+def bench_fp16(args):
+    """FP16 trailing updates with diagonal scaling (FP32 factor storage), FP64
+    refinement to a certified 1e-10: SE kernel d=8, lengthscale 0.5, variance 1,
+    noise 1, 8 right-hand sides, seed 0.  A is assembled in FP64 (lower part of
+    a full n x n array: 137 GB at n = 131072) and used for the residuals."""
+    import torch
+    import gp_inputs
+    import paper_2605_13209_amd as P
+    n = args.n or 131072
+    tile, k = 128, 8
+    hp = (0.5, 1.0, 1.0)
+    X, B = gp_inputs.gp_problem(n, d=8, k=k, seed=0)
+    Xd = torch.from_numpy(X).cuda()
+    Bd = P.to_colmajor(torch.from_numpy(B))
+    A = P.colmajor_empty(n, n)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    P.gp_assemble(Xd, *hp, full=False, out=A)
+    e1.record()
+    e1.synchronize()
+    t_asm = e0.elapsed_time(e1)
+    ws = torch.empty(P.chol_factor_bytes(n, "fp16_scaled", tile), dtype=torch.uint8, device="cuda")
+    out = P.colmajor_empty(n, k)
+    ts, tf, it, ce = [], [], [], []
+    for rep in range(args.warmup + args.steps):
+        torch.cuda.synchronize()
+        if rep == args.warmup and not args.no_profile:
+            P.chol_profile_reset()
+            P.set_option("profile", 2)
+        t0 = time.perf_counter()
+        F = P.chol_factor(A, "fp16_scaled", tile, workspace=ws, sync=False)
+        torch.cuda.synchronize()
+        tm = time.perf_counter()
+        r = P.chol_refine_solve(F, Bd, A=A, noise=hp[2], tol=1e-10, method="ir", max_iter=60, out=out)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        if F.info() != 0 or not r.converged:
+            raise RuntimeError(f"fp16 path failed: info={F.info()} converged={r.converged} iters={r.iters}")
+        if rep >= args.warmup:
+            ts.append((t1 - t0) * 1e3)
+            tf.append((tm - t0) * 1e3)
+            it.append(r.iters)
+            ce.append(r.cert)
+        del F
+    P.set_option("profile", 0)
+    flops = n ** 3 / 3
+    ms = float(np.mean(ts))
+    roofline = None
+    kms, kl, kfl = P.chol_profile_read()
+    if kl > 0 and kms > 0:
+        ach = kfl / (kms * 1e-3) / 1e12
+        roofline = {"bound": "mfma", "achieved": round(ach, 3), "peak": FP16_PEAK_TFLOPS,
+                    "unit": "TFLOP/s", "frac": round(ach / FP16_PEAK_TFLOPS, 4), "traffic": None,
+                    "kernel": "update_f16_kernel (Step-3 update of the trailing triangle)",
+                    "launches": kl, "avg_launch_us": round(kms * 1e3 / kl, 2),
+                    "avg_launch_gflop": round(kfl / kl / 1e9, 4)}
+    print(json.dumps({"metric": METRIC, "value": round(flops / (ms * 1e-3) / 1e9, 2), "unit": "GFLOP/s",
+                      "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 3),
+                      "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+                      "dtype": "f16+f32+f64", "data": "synthetic",
+                      "config": {"workload": f"mixed_fp16_n{n}", "n": n, "tile": tile, "rhs": k,
+                                 "kernel": "SE d=8 lengthscale=0.5 variance=1 noise=1", "seed": 0,
+                                 "tol": 1e-10, "precision": "fp16 trailing updates (scaled) + fp32 storage"
+                                                           " + fp64 IR"},
+                      "roofline": roofline,
+                      "ms": {"assemble": round(t_asm, 3), "factor": round(float(np.mean(tf)), 2),
+                             "time_to_solution": round(ms, 2)},
+                      "factor_gflops": round(flops / (np.mean(tf) * 1e-3) / 1e9, 1),
+                      "iters": int(max(it)), "cert": float(max(ce))}))
 
 
 def measured_traffic(n: int, dtype: str):

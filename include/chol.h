@@ -103,7 +103,8 @@ int gp_assemble(const double *X, int64_t n, int64_t d, int64_t ldx,
  * is stored as the paper stores it (Implementation section): only the
  * lower-triangular and diagonal square blocks, each block contiguous, plus
  * the N inverted diagonal blocks L_cc^{-T} that the solves apply (computed
- * once at the end of the factorisation).
+ * once at the end of the factorisation); CHOL_FP16_SCALED adds two FP16
+ * copies of a panel (N * 256 KB each) that its trailing updates read.
  * Returns 0 for invalid arguments.  Host-only; no device work.           */
 size_t chol_factor_bytes(int64_t n, int precision, int tile);
 

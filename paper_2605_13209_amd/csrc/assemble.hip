@@ -187,6 +187,22 @@ __global__ void clear_i64_kernel(int64_t *p, int count) {
   if (t < count) p[t] = 0;
 }
 
+// Largest diagonal entry of a column-major matrix (one workgroup; NaN-free
+// input assumed, non-positive results are left to the caller).
+__global__ __launch_bounds__(1024) void max_diag_kernel(const double *__restrict__ A, int64_t lda,
+                                                        int64_t n, double *__restrict__ out) {
+  __shared__ double sm[1024];
+  double m = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += 1024) m = fmax(m, A[i * (lda + 1)]);
+  sm[threadIdx.x] = m;
+  __syncthreads();
+  for (int w = 512; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) sm[threadIdx.x] = fmax(sm[threadIdx.x], sm[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = sm[0];
+}
+
 }  // namespace
 
 void launch_gp_assemble(const double *X, int64_t n, int64_t d, int64_t ldx, double two_l2,
@@ -207,6 +223,10 @@ void launch_gp_residual(const double *F, int64_t n, int64_t d, int64_t ldf, doub
   dim3 grid((unsigned)((n + 63) / 64), (unsigned)((nrhs + kResRhs - 1) / kResRhs));
   hipLaunchKernelGGL(gp_residual_kernel, grid, dim3(256), 0, s, F, n, (int)d, ldf, two_l2, var,
                      noise, Xs, ldxs, B, ldb, R, ldr, nrhs);
+}
+
+void launch_max_diag(const double *A, int64_t lda, int64_t n, double *out, hipStream_t s) {
+  hipLaunchKernelGGL(max_diag_kernel, dim3(1), dim3(1024), 0, s, A, lda, n, out);
 }
 
 void launch_clear_i64(int64_t *p, int count, hipStream_t s) {

@@ -19,69 +19,124 @@ __device__ inline void two_sum(double a, double b, double &s, double &e) {
 // 64 rows and walks every 64-column block of the symmetric matrix: blocks
 // left of the diagonal come from the lower triangle as stored, blocks right
 // of it from the lower triangle transposed (both read along columns, so the
-// HBM reads are contiguous), each staged through LDS.  Lane o of the four
-// waves accumulates row o over a quarter of the block's columns in
-// double-double (TwoProd by fma, TwoSum), so the residual's own rounding is
-// far below FP64 round-off of |A||x| even at n ~ 1e5.
+// HBM reads are contiguous).  Blocks are staged through two LDS buffers: the
+// next block is loaded into registers while the current one is used, one
+// barrier per block.  Lane o of the four waves accumulates row o over a
+// quarter of the block's columns in double-double (TwoProd by fma, TwoSum),
+// with two independent accumulators per right-hand side for instruction-level
+// parallelism, so the residual's own rounding is far below FP64 round-off of
+// |A||x| even at n ~ 1e5.  Every reduction has a fixed order.
 template <int NR>
 __global__ __launch_bounds__(256) void symm_residual_kernel(
     const double *__restrict__ A, int64_t lda, int64_t n, const double *__restrict__ X,
     int64_t ldx, const double *__restrict__ Bm, int64_t ldb, double *__restrict__ R, int64_t ldr,
     int64_t nrhs) {
   constexpr int P = 65;
-  __shared__ double at[64 * P];   // at[jj * P + ii] = A(I0 + ii, J0 + jj)
-  __shared__ double xs[64 * NR];  // xs[jj * NR + cc]
-  __shared__ double red_s[4 * 64 * NR], red_e[4 * 64 * NR];
+  constexpr int NA = 2;  // accumulators per right-hand side
+  __shared__ double at[2][64 * P];  // at[.][jj * P + ii] = A(I0 + ii, J0 + jj)
+  __shared__ double xs[2][64 * NR];  // xs[.][jj * NR + cc]
   const int tid = threadIdx.x, o = tid & 63, h = tid >> 6;
   const int64_t I0 = (int64_t)blockIdx.x * 64;
   const int64_t c0 = (int64_t)blockIdx.y * NR;
   const int nc = (int)min<int64_t>(NR, nrhs - c0);
-  double hs[NR], he[NR];
-#pragma unroll
-  for (int cc = 0; cc < NR; ++cc) hs[cc] = he[cc] = 0.0;
   const int64_t nb = (n + 63) / 64;
-  for (int64_t Jb = 0; Jb < nb; ++Jb) {
+  // block Jb into registers (16 values of A, up to NR/4 + 1 values of X)
+  constexpr int XV = (64 * NR + 255) / 256;
+  double ra[16], rx[XV];
+  auto fetch = [&](int64_t Jb) {
     const int64_t J0 = Jb * 64;
-    __syncthreads();
-    for (int e = tid; e < 64 * 64; e += 256) {
-      const int a = e & 63, bc = e >> 6;  // a: contiguous index in memory
-      if (J0 < I0) {  // lower block: value A(I0+a, J0+bc) stored at column J0+bc
-        const int64_t gi = I0 + a, gj = J0 + bc;
-        at[bc * P + a] = (gi < n && gj < n) ? A[gi + gj * lda] : 0.0;
-      } else if (J0 > I0) {  // upper block: A(I0+bc, J0+a) = stored A(J0+a, I0+bc)
-        const int64_t gi = I0 + bc, gj = J0 + a;
-        at[a * P + bc] = (gi < n && gj < n) ? A[gj + gi * lda] : 0.0;
-      } else if (a >= bc) {  // diagonal block: mirror the lower triangle
-        const int64_t gi = I0 + a, gj = I0 + bc;
-        const double v = (gi < n && gj < n) ? A[gi + gj * lda] : 0.0;
-        at[bc * P + a] = v;
-        at[a * P + bc] = v;
-      }
-    }
-    for (int e = tid; e < 64 * NR; e += 256) {
-      const int jj = e % 64, cc = e / 64;
-      const int64_t gj = J0 + jj;
-      xs[jj * NR + cc] = (gj < n && cc < nc) ? X[gj + (c0 + cc) * ldx] : 0.0;
-    }
-    __syncthreads();
-    for (int jj = h * 16; jj < h * 16 + 16; ++jj) {
-      const double av = at[jj * P + o];
 #pragma unroll
-      for (int cc = 0; cc < NR; ++cc) {
-        const double xv = xs[jj * NR + cc];
-        const double p = av * xv;
-        const double pe = fma(av, xv, -p);
-        double s1, e1;
-        two_sum(hs[cc], p, s1, e1);
-        hs[cc] = s1;
-        he[cc] += e1 + pe;
+    for (int x = 0; x < 16; ++x) {
+      const int e = tid + 256 * x, a = e & 63, bc = e >> 6;
+      double v = 0.0;
+      if (J0 < I0) {
+        const int64_t gi = I0 + a, gj = J0 + bc;
+        if (gi < n && gj < n) v = A[gi + gj * lda];
+      } else if (J0 > I0) {
+        const int64_t gi = I0 + bc, gj = J0 + a;
+        if (gi < n && gj < n) v = A[gj + gi * lda];
+      } else if (a >= bc) {
+        const int64_t gi = I0 + a, gj = I0 + bc;
+        if (gi < n && gj < n) v = A[gi + gj * lda];
+      }
+      ra[x] = v;
+    }
+#pragma unroll
+    for (int x = 0; x < XV; ++x) {
+      const int e = tid + 256 * x, jj = e % 64, cc = e / 64;
+      const int64_t gj = J0 + jj;
+      rx[x] = (e < 64 * NR && gj < n && cc < nc) ? X[gj + (c0 + cc) * ldx] : 0.0;
+    }
+  };
+  auto stash = [&](int64_t Jb, int buf) {
+    const int64_t J0 = Jb * 64;
+#pragma unroll
+    for (int x = 0; x < 16; ++x) {
+      const int e = tid + 256 * x, a = e & 63, bc = e >> 6;
+      if (J0 < I0) {
+        at[buf][bc * P + a] = ra[x];
+      } else if (J0 > I0) {
+        at[buf][a * P + bc] = ra[x];
+      } else if (a >= bc) {
+        at[buf][bc * P + a] = ra[x];
+        at[buf][a * P + bc] = ra[x];
       }
     }
+#pragma unroll
+    for (int x = 0; x < XV; ++x) {
+      const int e = tid + 256 * x, jj = e % 64, cc = e / 64;
+      if (e < 64 * NR) xs[buf][jj * NR + cc] = rx[x];
+    }
+  };
+  double hs[NA][NR], he[NA][NR];
+#pragma unroll
+  for (int u = 0; u < NA; ++u)
+#pragma unroll
+    for (int cc = 0; cc < NR; ++cc) hs[u][cc] = he[u][cc] = 0.0;
+  fetch(0);
+  stash(0, 0);
+  __syncthreads();
+  for (int64_t Jb = 0; Jb < nb; ++Jb) {
+    const int buf = (int)(Jb & 1);
+    if (Jb + 1 < nb) fetch(Jb + 1);
+    const double *ab = at[buf];
+    const double *xb = xs[buf];
+#pragma unroll
+    for (int j2 = 0; j2 < 16; j2 += NA) {
+#pragma unroll
+      for (int u = 0; u < NA; ++u) {
+        const int jj = h * 16 + j2 + u;
+        const double av = ab[jj * P + o];
+#pragma unroll
+        for (int cc = 0; cc < NR; ++cc) {
+          const double xv = xb[jj * NR + cc];
+          const double p = av * xv;
+          const double pe = fma(av, xv, -p);
+          double s1, e1;
+          two_sum(hs[u][cc], p, s1, e1);
+          hs[u][cc] = s1;
+          he[u][cc] += e1 + pe;
+        }
+      }
+    }
+    // the other buffer was last read in the previous block, before the barrier
+    if (Jb + 1 < nb) stash(Jb + 1, buf ^ 1);
+    __syncthreads();
   }
+  // fold the accumulators (fixed order), then the four quarters through LDS
+  double *red_s = at[0], *red_e = at[1];  // 4 * 64 * NR <= 64 * P doubles for NR <= 16
 #pragma unroll
   for (int cc = 0; cc < NR; ++cc) {
-    red_s[(h * 64 + o) * NR + cc] = hs[cc];
-    red_e[(h * 64 + o) * NR + cc] = he[cc];
+    double s = hs[0][cc], e = he[0][cc];
+#pragma unroll
+    for (int u = 1; u < NA; ++u) {
+      double s1, e1;
+      two_sum(s, hs[u][cc], s1, e1);
+      s = s1;
+      e += e1 + he[u][cc];
+    }
+    red_s[(h * 64 + o) * NR + cc] = s;
+    red_e[(h * 64 + o) * NR + cc] = e;
   }
   __syncthreads();
   if (h == 0) {

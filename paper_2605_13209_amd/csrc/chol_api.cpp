@@ -154,17 +154,18 @@ double update_flops(int b, int64_t N, int pw, int64_t k0, int64_t k1, int mode) 
 
 // launch_update, bracketed by events when profiling.
 void update(void *tiles, int st, int b, int64_t N, int64_t p0, int pw, int64_t k0, int64_t k1,
-            int mode, int S, int fp16, const int64_t *info, hipStream_t s, int64_t max_wg = 0) {
+            int mode, int S, int fp16, const int64_t *info, hipStream_t s, int64_t max_wg = 0,
+            const void *p16 = nullptr) {
   if (N - k0 <= 0 || (mode == 1 && k1 <= k0)) return;
   const int64_t prof = g_opt.profile;
   if (!prof || (prof == 2 && mode != 0)) {
-    launch_update(tiles, st, b, N, p0, pw, k0, k1, mode, S, fp16, info, s, max_wg);
+    launch_update(tiles, st, b, N, p0, pw, k0, k1, mode, S, fp16, info, s, max_wg, p16);
     return;
   }
   std::lock_guard<std::mutex> lk(g_prof_mu);
   hipEvent_t a = prof_event(), e = prof_event();
   if (a) (void)hipEventRecord(a, s);
-  launch_update(tiles, st, b, N, p0, pw, k0, k1, mode, S, fp16, info, s, max_wg);
+  launch_update(tiles, st, b, N, p0, pw, k0, k1, mode, S, fp16, info, s, max_wg, p16);
   if (e) (void)hipEventRecord(e, s);
   if (a && e) g_prof.push_back({a, e, update_flops(b, N, pw, k0, k1, mode)});
 }
@@ -180,6 +181,7 @@ struct chol_factor_s {
   int b = 0, precision = 0, device = 0;
   void *tiles = nullptr;
   void *dinv = nullptr;  // inverted diagonal blocks L_cc^{-T} (the solves)
+  void *p16 = nullptr;   // CHOL_FP16_SCALED: two FP16 panel buffers (alternating panels)
   int64_t *d_info = nullptr;
   double scale = 1.0;  // CHOL_FP16_SCALED: the factor of A / scale is stored
   hipStream_t stream = nullptr;
@@ -288,9 +290,11 @@ size_t chol_factor_bytes(int64_t n, int precision, int tile) {
   if (tile == 0) tile = chol_tile_default(n, precision);
   if (!tile_ok(tile)) return 0;
   const int64_t N = (n + tile - 1) / tile;
-  // packed lower tiles, then the N transposed diagonal blocks
+  // packed lower tiles, then the N inverted diagonal blocks, then (FP16 form)
+  // two FP16 panel buffers
   return kHeader +
-         (size_t)(tile_count(N) + N) * (size_t)tile * (size_t)tile * esize_of(precision);
+         (size_t)(tile_count(N) + N) * (size_t)tile * (size_t)tile * esize_of(precision) +
+         (precision == CHOL_FP16_SCALED ? 2 * (size_t)N * (size_t)kP16BytesPerTileRow : 0);
 }
 
 int gp_assemble(const double *X, int64_t n, int64_t d, int64_t ldx, double lengthscale,
@@ -311,17 +315,27 @@ int gp_assemble(const double *X, int64_t n, int64_t d, int64_t ldx, double lengt
   return hipGetLastError() == hipSuccess ? CHOL_OK : CHOL_ERR_HIP;
 }
 
-// Steps 1-2 (and the in-panel Step 3) of panel columns [c0, c1).
-static void factor_panel(chol_factor_s *F, int64_t c0, int64_t c1, int st, hipStream_t s) {
+// FP16 panel buffer of the panel starting at column c0 (panels of width w
+// alternate between the two buffers).
+static void *panel_buf(const chol_factor_s *F, int64_t c0, int64_t w) {
+  if (!F->p16) return nullptr;
+  return (char *)F->p16 + (size_t)((c0 / w) & 1) * (size_t)F->N * (size_t)kP16BytesPerTileRow;
+}
+
+// Steps 1-2 (and the in-panel Step 3, in the storage precision) of panel
+// columns [c0, c1); in the FP16 form the finished panel is then converted
+// for the updates that use it.
+static void factor_panel(chol_factor_s *F, int64_t c0, int64_t c1, int64_t w, int st,
+                         hipStream_t s) {
   const int64_t N = F->N;
   const int b = F->b;
-  const int fp16 = F->precision == CHOL_FP16_SCALED;
   for (int64_t c = c0; c < c1; ++c) {
     launch_potrf(F->tiles, st, b, N, c, F->d_info, s);
     launch_trsm(F->tiles, st, b, N, c, F->d_info, s);
     if (c + 1 < c1)
-      update(F->tiles, st, b, N, c, 1, c + 1, c1, /*band*/ 1, 8, fp16, F->d_info, s);
+      update(F->tiles, st, b, N, c, 1, c + 1, c1, /*band*/ 1, 8, /*fp16*/ 0, F->d_info, s);
   }
+  if (F->p16) launch_panel_f16(F->tiles, N, c0, (int)(c1 - c0), panel_buf(F, c0, w), F->d_info, s);
 }
 
 // Enqueue the whole factorisation (clear info, pack, column steps) on the
@@ -337,15 +351,16 @@ static int enqueue_factor(chol_factor_s *F, SideCtx *ctx, const double *A, int64
   if (!la) {
     for (int64_t c0 = 0; c0 < N; c0 += w) {
       const int64_t c1 = std::min<int64_t>(c0 + w, N);
-      factor_panel(F, c0, c1, st, s);
+      factor_panel(F, c0, c1, w, st, s);
       if (c1 < N)
-        update(F->tiles, st, b, N, c0, (int)(c1 - c0), c1, N, /*tri*/ 0, S, fp16, F->d_info, s);
+        update(F->tiles, st, b, N, c0, (int)(c1 - c0), c1, N, /*tri*/ 0, S, fp16, F->d_info, s, 0,
+               panel_buf(F, c0, w));
     }
   } else {
     hipStream_t p = ctx->side;
     HIP_OK(hipEventRecord(ctx->ev_fork, s));
     HIP_OK(hipStreamWaitEvent(p, ctx->ev_fork, 0));
-    factor_panel(F, 0, std::min<int64_t>(w, N), st, p);
+    factor_panel(F, 0, std::min<int64_t>(w, N), w, st, p);
     for (int64_t c0 = 0; c0 < N; c0 += w) {
       const int64_t c1 = std::min<int64_t>(c0 + w, N);  // current panel [c0, c1)
       const int64_t n1 = std::min<int64_t>(c1 + w, N);  // next panel [c1, n1)
@@ -354,8 +369,9 @@ static int enqueue_factor(chol_factor_s *F, SideCtx *ctx, const double *A, int64
         // next panel: its update by this panel (after the previous bulk update,
         // which also wrote it), then its Steps 1-2, all on the side stream.
         if (c0 > 0) HIP_OK(hipStreamWaitEvent(p, ctx->ev_bulk, 0));
-        update(F->tiles, st, b, N, c0, (int)(c1 - c0), c1, n1, /*band*/ 1, 8, fp16, F->d_info, p);
-        factor_panel(F, c1, n1, st, p);
+        update(F->tiles, st, b, N, c0, (int)(c1 - c0), c1, n1, /*band*/ 1, 8, fp16, F->d_info, p, 0,
+               panel_buf(F, c0, w));
+        factor_panel(F, c1, n1, w, st, p);
       }
       // bulk update of the columns right of the next panel, on the main
       // stream; while a next panel exists its workgroups are capped so that
@@ -363,7 +379,7 @@ static int enqueue_factor(chol_factor_s *F, SideCtx *ctx, const double *A, int64
       HIP_OK(hipStreamWaitEvent(s, ctx->ev_panel, 0));
       if (n1 < N) {
         update(F->tiles, st, b, N, c0, (int)(c1 - c0), n1, N, /*tri*/ 0, S, fp16, F->d_info, s,
-               g_opt.bulk_wg_cap.load());
+               g_opt.bulk_wg_cap.load(), panel_buf(F, c0, w));
       }
       HIP_OK(hipEventRecord(ctx->ev_bulk, s));
     }
@@ -412,6 +428,8 @@ int chol_factor_ex(const double *A, int64_t n, int64_t lda, int precision,
   F->d_info = (int64_t *)workspace;
   F->tiles = (char *)workspace + kHeader;
   F->dinv = (char *)F->tiles + (size_t)tile_count(F->N) * (size_t)tile * tile * esize_of(precision);
+  if (precision == CHOL_FP16_SCALED)
+    F->p16 = (char *)F->dinv + (size_t)F->N * (size_t)tile * tile * esize_of(precision);
   F->stream = (hipStream_t)stream;
   const int st = store_of(precision);
   const int64_t N = F->N;
@@ -419,15 +437,15 @@ int chol_factor_ex(const double *A, int64_t n, int64_t lda, int precision,
   hipStream_t s = F->stream;
 
   // Scaling for the FP16 form: the factor of H = A / s is computed, with s
-  // the largest diagonal entry (one read-back of the diagonal).
+  // the largest diagonal entry (reduced on the device into the workspace
+  // header, then one 8-byte read-back).
   double pack_scale = 1.0;
   if (precision == CHOL_FP16_SCALED && n > 0) {
-    std::vector<double> diag((size_t)n);
-    HIP_OK(hipStreamSynchronize(s));
-    HIP_OK(hipMemcpy2D(diag.data(), sizeof(double), A, (size_t)(lda + 1) * sizeof(double),
-                       sizeof(double), (size_t)n, hipMemcpyDeviceToHost));
+    double *d_mx = (double *)((char *)workspace + 64);
+    launch_max_diag(A, lda, n, d_mx, s);
     double mx = 0.0;
-    for (double v : diag) mx = std::fmax(mx, v);
+    HIP_OK(hipMemcpyAsync(&mx, d_mx, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
     if (!(mx > 0.0)) mx = 1.0;
     F->scale = mx;
     pack_scale = 1.0 / mx;

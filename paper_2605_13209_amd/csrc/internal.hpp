@@ -40,6 +40,8 @@ void launch_gp_residual(const double *F, int64_t n, int64_t d, int64_t ldf, doub
 
 // Clear the info word (a kernel, not a memset, so graph capture is safe).
 void launch_clear_i64(int64_t *p, int count, hipStream_t s);
+// *out = max_i A(i, i) (column-major, leading dimension lda).
+void launch_max_diag(const double *A, int64_t lda, int64_t n, double *out, hipStream_t s);
 
 // Column-major FP64 A (lower) -> packed tiles, scaled by `scale`, identity padding.
 void launch_pack(const double *A, int64_t n, int64_t lda, void *tiles, int store, int b,
@@ -57,12 +59,19 @@ void launch_trsm(void *tiles, int store, int b, int64_t N, int64_t c, const int6
 // Step 3: C_ik -= sum_{p in [p0, p0+pw)} L_ip L_kp^T over the region
 //   mode 0 (triangle): k0 <= k <= i < N;
 //   mode 1 (band)    : k in [k0, k1), k <= i < N  (k1 - k0 <= super_tile).
-// fp16 = 1 rounds the panel operands to FP16 (FP32 storage only).
+// fp16 = 1 takes the panel operands in FP16 from p16, the panel converted
+// by launch_panel_f16 (FP32 storage, tile 128 only).
 // max_wg > 0 caps the number of workgroups (each then walks several tiles),
 // leaving workgroup slots free for kernels on other streams.
 void launch_update(void *tiles, int store, int b, int64_t N, int64_t p0, int pw, int64_t k0,
                    int64_t k1, int mode, int super_tile, int fp16, const int64_t *info,
-                   hipStream_t s, int64_t max_wg = 0);
+                   hipStream_t s, int64_t max_wg = 0, const void *p16 = nullptr);
+// FP16 copy of the finished panel columns [c0, c0 + pw) for tile rows
+// [c0, N), in the update kernel's layout: p16 holds N * 16 chunks of
+// 128 x 64 halves (panel width <= 8).
+constexpr int64_t kP16BytesPerTileRow = 16 * 128 * 64 * 2;
+void launch_panel_f16(const void *tiles, int64_t N, int64_t c0, int pw, void *p16,
+                      const int64_t *info, hipStream_t s);
 
 // After the factorisation: block c of dinv (N blocks of b x b) = L_cc^{-T}.
 void launch_diag_inverse(const void *tiles, int store, int b, int64_t N, void *dinv,

@@ -324,113 +324,151 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void u
 }
 
 // --------------------------------------------------- FP16 operands (FP32 C) --
-// Panel tiles are FP32 in memory; each chunk is rounded to FP16 when staged.
-// v_mfma_f32_16x16x32_f16: lane (g, q) supplies A[row q][k = 8g .. 8g+7] and
-// B[k = 8g .. 8g+7][col q]; LDS keeps the chunk k-contiguous per row
-// ([row][k], KC16 = 32 halves = 64 bytes per row, padded), so each fragment
-// is one 16-byte read.  Rows are interleaved across MFMA blocks as above.
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void update_f16_kernel(
-    float *__restrict__ tiles, int64_t N, int64_t p0, int pw, int64_t k0, int64_t K, int mode,
-    int S, int64_t G, int64_t G8, const int64_t *__restrict__ info) {
-  constexpr int KC16 = 32;            // k per chunk
-  constexpr int RP = KC16 + 8;        // LDS row pitch in halves (80 bytes)
-  if (*info != 0) return;
-  __shared__ __attribute__((aligned(16))) _Float16 lds[2][2][BT * RP];
-  // Persistent: workgroup w walks the tiles of XCD range w mod 8 (positions
-  // w/8, w/8 + per, ...), so the grid may be smaller than the tile count.
-  const int64_t per = gridDim.x / 8;
-  for (int64_t pos = blockIdx.x / 8; pos < G8; pos += per) {
-  const int64_t t = (blockIdx.x % 8) * G8 + pos;
-  if (t >= G) break;
-  int64_t ir, kr;
-  if (mode == 0)
-    map_triangle(t, N - k0, S, ir, kr);
-  else
-    map_band(t, K, ir, kr);
-  const int64_t i = k0 + ir, k = k0 + kr;
+// The FP16 form converts each finished panel once (panel_f16_kernel) into a
+// buffer laid out for the update: for tile row i and chunk ch (64 panel
+// columns), 128 rows x 128 bytes, row r's 16-byte segment s (k = 8s .. 8s+7)
+// stored at position s ^ ((r >> 2) & 7).  The update kernel then DMAs 16 KB
+// chunks straight into LDS, and its fragment reads (v_mfma_f32_16x16x32_f16:
+// lane (g, q) supplies A[row q][k = 8g .. 8g+7]; rows interleaved as in the
+// FP32 kernel, wave-local row 4q + s2) hit 8 different 16-byte bank groups
+// per 8 lanes.  Converting once per panel instead of once per use also
+// removes the transpose from the update's inner loop.
+constexpr int P16_CHMAX = 16;  // chunks of 64 columns per tile row (panel width <= 8)
+constexpr int P16_CHUNK = BT * 64;  // halves per chunk
 
+__global__ __launch_bounds__(256) void panel_f16_kernel(const float *__restrict__ tiles, int64_t N,
+                                                        int64_t c0, _Float16 *__restrict__ p16,
+                                                        const int64_t *__restrict__ info) {
+  if (*info != 0) return;
+  constexpr int PAD = BT + 1;
+  __shared__ float st[64 * PAD];  // [column][row]
+  const int64_t i = c0 + blockIdx.x;
+  const int ch = blockIdx.y;
+  const int64_t p = c0 + ch / 2;
+  const int t = threadIdx.x;
+  if (p <= i) {
+    const float *src = tiles + tile_index(i, p, N) * (int64_t)(BT * BT) + (ch % 2) * 64 * BT;
+    for (int e = t; e < 64 * BT; e += 256) st[(e / BT) * PAD + e % BT] = src[e];
+  } else {
+    for (int e = t; e < 64 * BT; e += 256) st[(e / BT) * PAD + e % BT] = 0.0f;
+  }
+  __syncthreads();
+  _Float16 *dst = p16 + (i * P16_CHMAX + ch) * (int64_t)P16_CHUNK;
+#pragma unroll
+  for (int x = 0; x < 4; ++x) {
+    const int e = t + 256 * x, r = e / 8, sg = e % 8;
+    v8h v;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) v[j] = (_Float16)st[(8 * sg + j) * PAD + r];
+    *(v8h *)(dst + r * 64 + 8 * (sg ^ ((r >> 2) & 7))) = v;
+  }
+}
+
+// Trailing update with FP16 operands from the converted panel and FP32 C
+// (accumulators start at -C).  Same structure as the FP32 kernel: chunks of
+// 64 panel columns DMA'd two ahead, next k-step's fragments read during the
+// current MFMAs, one barrier per chunk (after its first of two k-steps).
+template <int REGION>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void update_f16_kernel(
+    float *__restrict__ tiles, const _Float16 *__restrict__ p16, int64_t N, int pw, int64_t k0,
+    int64_t K, int S, int64_t G, int64_t G8, const int64_t *__restrict__ info) {
+  constexpr int NKS = 2;  // k-steps of 32 per chunk
+  if (*info != 0) return;
+  __shared__ __attribute__((aligned(16))) _Float16 lds[2][2][P16_CHUNK];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int g = lane >> 4, q = lane & 15;
   const int wm = wave >> 1, wn = wave & 1;
-  float *C = tiles + tile_index(i, k, N) * (int64_t)(BT * BT);
-
-  v4f acc[4][4];
-  {
-    const int r0 = 64 * wm + 16 * g;
+  const int wu = __builtin_amdgcn_readfirstlane(wave);
+  const int64_t per = gridDim.x / 8;  // persistent, as in the FP64 kernel
+  for (int64_t pos = blockIdx.x / 8; pos < G8; pos += per) {
+    const int64_t t = (blockIdx.x % 8) * G8 + pos;
+    if (t >= G) break;
+    int64_t ir, kr;
+    if (REGION == 0)
+      map_triangle(t, N - k0, S, ir, kr);
+    else
+      map_band(t, K, ir, kr);
+    const int64_t i = k0 + ir, k = k0 + kr;
+    float *C = tiles + tile_index(i, k, N) * (int64_t)(BT * BT);
+    const int nstage = 2 * pw;
+    // chunk s: 16 KB per operand; wave w moves KB w*4 .. w*4+3 of both
+    auto dma = [&](int s) {
+      const _Float16 *pa = p16 + (i * P16_CHMAX + s) * (int64_t)P16_CHUNK;
+      const _Float16 *pb = p16 + (k * P16_CHMAX + s) * (int64_t)P16_CHUNK;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const int off = (wu * 4 + c) * 512;  // halves (1 KB)
+        lds_dma16(pa + off, lane * 16, &lds[s & 1][0][off]);
+        lds_dma16(pb + off, lane * 16, &lds[s & 1][1][off]);
+      }
+    };
+    v4f acc[4][4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      const float *src = C + (64 * wn + 4 * q + u) * BT + r0;
-      float v[16];
+      const float *col = C + (64 * wn + 4 * q + u) * BT + 64 * wm + 16 * g;
 #pragma unroll
-      for (int x = 0; x < 4; ++x) *(uint4 *)&v[x * 4] = *(const uint4 *)(src + x * 4);
+      for (int e = 0; e < 4; ++e) {
+        float v[4];
+        *(uint4 *)&v[0] = *(const uint4 *)(col + 4 * e);
 #pragma unroll
-      for (int rho = 0; rho < 16; ++rho) acc[rho & 3][u][rho >> 2] = v[rho];
-    }
-  }
-  // Chunk = 32 columns x 128 rows of FP32 = 4096 floats = 1024 float4 per operand;
-  // each thread loads 4 float4 of A and of B.  Thread -> (column kk, rows r..r+3).
-  const int nstage = pw * (BT / KC16);
-  float4 ra[4], rb[4];
-  auto gload = [&](int s) {
-    const int64_t p = p0 + (s * KC16) / BT;
-    const int col0 = (s * KC16) % BT;
-    const float *pa = tiles + tile_index(i, p, N) * (int64_t)(BT * BT) + col0 * BT;
-    const float *pb = tiles + tile_index(k, p, N) * (int64_t)(BT * BT) + col0 * BT;
-#pragma unroll
-    for (int x = 0; x < 4; ++x) {
-      const int v = tid + 256 * x;
-      ra[x] = *(const float4 *)(pa + v * 4);
-      rb[x] = *(const float4 *)(pb + v * 4);
-    }
-  };
-  auto lstore = [&](int buf) {
-#pragma unroll
-    for (int x = 0; x < 4; ++x) {
-      const int e = (tid + 256 * x) * 4;
-      const int kk = e / BT, r = e % BT;
-      const float av[4] = {ra[x].x, ra[x].y, ra[x].z, ra[x].w};
-      const float bv[4] = {rb[x].x, rb[x].y, rb[x].z, rb[x].w};
-#pragma unroll
-      for (int y = 0; y < 4; ++y) {
-        lds[buf][0][(r + y) * RP + kk] = (_Float16)(-av[y]);
-        lds[buf][1][(r + y) * RP + kk] = (_Float16)bv[y];
+        for (int s2 = 0; s2 < 4; ++s2) acc[s2][u][e] = -v[s2];
       }
     }
-  };
-  gload(0);
-  lstore(0);
-  __syncthreads();
-  for (int s = 0; s < nstage; ++s) {
-    const int buf = s & 1;
-    if (s + 1 < nstage) gload(s + 1);
-    const _Float16 *la = &lds[buf][0][0];
-    const _Float16 *lb = &lds[buf][1][0];
-    v8h a[4], b[4];
-#pragma unroll
-    for (int s2 = 0; s2 < 4; ++s2) {
-      a[s2] = *(const v8h *)(la + (64 * wm + 4 * q + s2) * RP + 8 * g);
-      b[s2] = *(const v8h *)(lb + (64 * wn + 4 * q + s2) * RP + 8 * g);
-    }
-#pragma unroll
-    for (int s2 = 0; s2 < 4; ++s2)
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-        acc[s2][u] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a[s2], b[u], acc[s2][u], 0, 0, 0);
-    if (s + 1 < nstage) lstore(buf ^ 1);
+    dma(0);
+    if (nstage > 1) dma(1);
+    wait_vmem();
     __syncthreads();
-  }
-  {
-    const int r0 = 64 * wm + 16 * g;
+    // fragment of wave-local row 4q + s2 (operand base row r0), k-step ks
+    auto frag = [&](const _Float16 *l, int r0, int s2, int ks) -> v8h {
+      const int r = r0 + 4 * q + s2;
+      const int sg = (4 * ks + g) ^ ((r >> 2) & 7);
+      return *(const v8h *)(l + r * 64 + 8 * sg);
+    };
+    v8h fa[2][4], fb[2][4];
+#pragma unroll
+    for (int x = 0; x < 4; ++x) {
+      fa[0][x] = frag(lds[0][0], 64 * wm, x, 0);
+      fb[0][x] = frag(lds[0][1], 64 * wn, x, 0);
+    }
+    const int nk = nstage * NKS;
+    auto step = [&](int kt, int cur) {
+      const int s = kt / NKS, ks = kt % NKS;
+      const int nbuf = ((kt + 1) / NKS) & 1, nks = (kt + 1) % NKS;
+#pragma unroll
+      for (int x = 0; x < 4; ++x) {  // next k-step (stale but in-bounds after the last)
+        fa[cur ^ 1][x] = frag(lds[nbuf][0], 64 * wm, x, nks);
+        fb[cur ^ 1][x] = frag(lds[nbuf][1], 64 * wn, x, nks);
+      }
+#pragma unroll
+      for (int s2 = 0; s2 < 4; ++s2)
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          acc[s2][u] =
+              __builtin_amdgcn_mfma_f32_16x16x32_f16(fa[cur][s2], fb[cur][u], acc[s2][u], 0, 0, 0);
+      __builtin_amdgcn_sched_group_barrier(0x100, 8, 0);
+      __builtin_amdgcn_sched_group_barrier(0x008, 16, 0);
+      __builtin_amdgcn_sched_barrier(0);
+      if (ks == NKS - 2) {
+        wait_vmem();
+        __syncthreads();
+        if (s + 2 < nstage) dma(s + 2);
+      }
+    };
+    for (int kt = 0; kt < nk; kt += 2) {
+      step(kt, 0);
+      step(kt + 1, 1);
+    }
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      float *dst = C + (64 * wn + 4 * q + u) * BT + r0;
-      float v[16];
+      float *col = C + (64 * wn + 4 * q + u) * BT + 64 * wm + 16 * g;
 #pragma unroll
-      for (int rho = 0; rho < 16; ++rho) v[rho] = acc[rho & 3][u][rho >> 2];
+      for (int e = 0; e < 4; ++e) {
+        float v[4];
 #pragma unroll
-      for (int x = 0; x < 4; ++x) *(uint4 *)(dst + x * 4) = *(const uint4 *)&v[x * 4];
+        for (int s2 = 0; s2 < 4; ++s2) v[s2] = -acc[s2][u][e];
+        *(uint4 *)(col + 4 * e) = *(const uint4 *)&v[0];
+      }
     }
-  }
   }  // tiles of this workgroup
 }
 
@@ -485,7 +523,7 @@ __global__ __launch_bounds__(256) void update64_kernel(T *__restrict__ tiles, in
 
 void launch_update(void *tiles, int store, int b, int64_t N, int64_t p0, int pw, int64_t k0,
                    int64_t k1, int mode, int super_tile, int fp16, const int64_t *info,
-                   hipStream_t s, int64_t max_wg) {
+                   hipStream_t s, int64_t max_wg, const void *p16) {
   const int64_t R = N - k0;
   if (R <= 0 || pw <= 0) return;
   const int64_t K = k1 - k0;
@@ -502,9 +540,13 @@ void launch_update(void *tiles, int store, int b, int64_t N, int64_t p0, int pw,
     int64_t nwg = 8 * G8;
     if (max_wg >= 8 && nwg > max_wg) nwg = (max_wg / 8) * 8;  // persistent: fewer workgroups
     const dim3 grid((unsigned)nwg);
-    if (fp16)
-      hipLaunchKernelGGL(update_f16_kernel, grid, dim3(256), 0, s, (float *)tiles, N, p0, pw, k0,
-                         K, mode, super_tile, G, G8, info);
+    if (fp16 && !p16) return;  // the FP16 form needs its converted panel
+    if (fp16 && mode == 0)
+      hipLaunchKernelGGL(update_f16_kernel<0>, grid, dim3(256), 0, s, (float *)tiles,
+                         (const _Float16 *)p16, N, pw, k0, K, super_tile, G, G8, info);
+    else if (fp16)
+      hipLaunchKernelGGL(update_f16_kernel<1>, grid, dim3(256), 0, s, (float *)tiles,
+                         (const _Float16 *)p16, N, pw, k0, K, super_tile, G, G8, info);
     else if (store == STORE_F64 && mode == 0)
       hipLaunchKernelGGL(update_f64_kernel<0>, grid, dim3(256), 0, s, (double *)tiles, N, p0, pw,
                          k0, K, super_tile, G, G8, info);
@@ -526,6 +568,13 @@ void launch_update(void *tiles, int store, int b, int64_t N, int64_t p0, int pw,
       hipLaunchKernelGGL(update64_kernel<float>, grid, dim3(256), 0, s, (float *)tiles, N, p0, pw,
                          k0, K, mode, super_tile, G, info);
   }
+}
+
+void launch_panel_f16(const void *tiles, int64_t N, int64_t c0, int pw, void *p16,
+                      const int64_t *info, hipStream_t s) {
+  if (N - c0 <= 0 || pw <= 0) return;
+  hipLaunchKernelGGL(panel_f16_kernel, dim3((unsigned)(N - c0), (unsigned)(2 * pw)), dim3(256), 0,
+                     s, (const float *)tiles, N, c0, (_Float16 *)p16, info);
 }
 
 }  // namespace chol

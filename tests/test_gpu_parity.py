@@ -340,6 +340,23 @@ def test_fp16_scaled_factor_and_refine():
             assert err <= 1e-10, (method, c, err)
 
 
+@pytest.mark.parametrize("pw", [2, 3])
+def test_fp16_scaled_lookahead_invariance(pw):
+    # the two FP16 panel buffers alternate between panels; with and without
+    # lookahead (ragged n, a partial last panel) the factors are identical
+    n = 1300
+    X, _ = gp_inputs.gp_problem(n, seed=4)
+    Ad = P.gp_assemble(torch.from_numpy(X).cuda(), 0.5, 1.0, 1.0)
+    Ls = []
+    for la in (0, 1):
+        F = P.chol_factor(Ad, "fp16_scaled", 128, panel_width=pw, lookahead=la)
+        assert F.info() == 0
+        Ls.append(host(P.chol_factor_to_dense(F)))
+    assert np.array_equal(Ls[0], Ls[1])
+    be = oracle.backward_error(oracle.gp_assemble(X, 0.5, 1.0, 1.0), Ls[0])
+    assert be <= 5e-3, be
+
+
 def test_fp16_scaled_solve_scaling():
     """chol_solve with the scaled factor returns A^-1 b (not H^-1 b)."""
     n = 600
