@@ -22,6 +22,31 @@ __device__ inline double readlane_f64(double v, int l) {
   return __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
 }
 
+// x L^T = rhs for one row x of 16 values against a 16 x 16 lower block L in
+// LDS (row pitch PP) with reciprocal diagonal rdv: column by column, x_j is
+// scaled and then subtracted from the later x_i (the same operations in the
+// same order as the row-wise substitution), column j + 1 of L being read
+// while column j is applied.
+template <int NB, int PP>
+__device__ __forceinline__ void row_solve(double (&x)[NB], const double *l, const double *rdv) {
+  double rv[NB], col[2][NB];
+#pragma unroll
+  for (int j = 0; j < NB; ++j) rv[j] = rdv[j];
+#pragma unroll
+  for (int i = 1; i < NB; ++i) col[0][i] = l[i * PP];
+#pragma unroll
+  for (int j = 0; j < NB; ++j) {
+    if (j + 1 < NB) {
+#pragma unroll
+      for (int i = j + 2; i < NB; ++i) col[(j + 1) & 1][i] = l[i * PP + j + 1];
+    }
+    x[j] *= rv[j];
+#pragma unroll
+    for (int i = j + 1; i < NB; ++i) x[i] -= x[j] * col[j & 1][i];
+    __builtin_amdgcn_sched_barrier(0);
+  }
+}
+
 // One workgroup of 256 threads factors a B x B diagonal tile in FP64,
 // blocked by 16 columns (right-looking).  The trailing part of the tile lives
 // in registers: threads form a 16 x 16 grid and thread (tr, tc) owns the
@@ -66,19 +91,34 @@ __global__ __launch_bounds__(256) void potrf_kernel(T *__restrict__ tiles, int64
   const int t = threadIdx.x, tc = t & 15, tr = t >> 4;
   if (t == 0) fail = 0;
   double a[M][M];
+  {
+    // all loads of a quarter are issued before any LDS store (one latency per quarter)
+    constexpr int QV = QC * B / 256;
+    T nxt[QV];
 #pragma unroll
-  for (int q4 = 0; q4 < B / QC; ++q4) {
-    for (int e = t; e < QC * B; e += 256) {
-      const int r = e % B, cc = e / B;
-      stage[cc * LD + r] = (double)tile[(q4 * QC + cc) * B + r];
+    for (int x = 0; x < QV; ++x) nxt[x] = tile[t + 256 * x];
+#pragma unroll
+    for (int q4 = 0; q4 < B / QC; ++q4) {
+      T cur[QV];
+#pragma unroll
+      for (int x = 0; x < QV; ++x) cur[x] = nxt[x];
+      if (q4 + 1 < B / QC) {
+#pragma unroll
+        for (int x = 0; x < QV; ++x) nxt[x] = tile[(q4 + 1) * QC * B + t + 256 * x];
+      }
+#pragma unroll
+      for (int x = 0; x < QV; ++x) {
+        const int e = t + 256 * x, r = e % B, cc = e / B;
+        stage[cc * LD + r] = (double)cur[x];
+      }
+      __syncthreads();
+#pragma unroll
+      for (int m = 0; m < M; ++m)
+#pragma unroll
+        for (int nn = 0; nn < 2; ++nn)
+          a[m][2 * q4 + nn] = stage[(tc + 16 * nn) * LD + tr + 16 * m];
+      __syncthreads();
     }
-    __syncthreads();
-#pragma unroll
-    for (int m = 0; m < M; ++m)
-#pragma unroll
-      for (int nn = 0; nn < 2; ++nn)
-        a[m][2 * q4 + nn] = stage[(tc + 16 * nn) * LD + tr + 16 * m];
-    __syncthreads();
   }
 
 #pragma unroll 1
@@ -101,8 +141,11 @@ __global__ __launch_bounds__(256) void potrf_kernel(T *__restrict__ tiles, int64
           if (!bad) bad = k + 1;
           d = 1.0;  // keep going without NaNs; the result is discarded
         }
+        // sqrt and its reciprocal computed independently (two short chains
+        // instead of one long one); both are exact for the powers of four
+        // of exact-arithmetic inputs
         const double lkk = sqrt(d);
-        const double rl = 1.0 / lkk;
+        const double rl = rsqrt(d);
         x[k] = (l == k) ? lkk : (l > k ? x[k] * rl : x[k]);
         if (l == k) rd[k] = rl;
         if (l < NB) cb[l] = x[k];
@@ -133,14 +176,7 @@ __global__ __launch_bounds__(256) void potrf_kernel(T *__restrict__ tiles, int64
         double x[NB];
 #pragma unroll
         for (int j = 0; j < NB; j += 2) *(double2 *)&x[j] = *(const double2 *)&pn[t * PP + j];
-#pragma unroll
-        for (int j = 0; j < NB; ++j) {
-          double s = x[j];
-#pragma unroll
-          for (int i = 0; i < j; ++i) s -= x[i] * dg[j * PP + i];
-          x[j] = s * rd[j];
-          __builtin_amdgcn_sched_barrier(0);
-        }
+        row_solve<NB, PP>(x, dg, rd);
 #pragma unroll
         for (int j = 0; j < NB; j += 2) *(double2 *)&pn[t * PP + j] = *(const double2 *)&x[j];
       }
@@ -226,20 +262,52 @@ __device__ __forceinline__ void trsm_tile(const T *__restrict__ L, T *__restrict
       if (e < rows * NB) ls[q & 1][r * PP + u] = v[x];
     }
   };
+  double a[M][M];
+  if (IDENT) {
+#pragma unroll
+    for (int m = 0; m < M; ++m)
+#pragma unroll
+      for (int n = 0; n < M; ++n) a[m][n] = (tr + 16 * m == tc + 16 * n) ? 1.0 : 0.0;
+  } else {
+    // the tile into registers through LDS (the L buffers, not yet in use), a
+    // quarter of 32 columns at a time with contiguous reads, the next
+    // quarter's loads in flight while the current one is redistributed
+    constexpr int QC = 32, LD = B + 1, QV = QC * B / 256;
+    static_assert(QC * LD <= 2 * B * PP, "staging fits in the L buffers");
+    double *stg = &ls[0][0];
+    T nxt[QV];
+#pragma unroll
+    for (int x = 0; x < QV; ++x) nxt[x] = X[t + 256 * x];
+#pragma unroll
+    for (int q4 = 0; q4 < B / QC; ++q4) {
+      T cur[QV];
+#pragma unroll
+      for (int x = 0; x < QV; ++x) cur[x] = nxt[x];
+      if (q4 + 1 < B / QC) {
+#pragma unroll
+        for (int x = 0; x < QV; ++x) nxt[x] = X[(int64_t)(q4 + 1) * QC * B + t + 256 * x];
+      }
+      if (q4 > 0) __syncthreads();  // previous quarter fully read
+#pragma unroll
+      for (int x = 0; x < QV; ++x) {
+        const int e = t + 256 * x, r = e % B, cc = e / B;
+        stg[cc * LD + r] = (double)cur[x];
+      }
+      __syncthreads();
+#pragma unroll
+      for (int m = 0; m < M; ++m)
+#pragma unroll
+        for (int nn = 0; nn < 2; ++nn)
+          a[m][2 * q4 + nn] = stg[(tc + 16 * nn) * LD + tr + 16 * m];
+    }
+    __syncthreads();  // staging done before the L buffers are filled
+  }
   {
     double v[PF];
     lget(0, v);
     lput(0, v);
   }
   for (int e = t; e < B; e += 256) rdl[e] = 1.0 / (double)L[(int64_t)e * B + e];
-  double a[M][M];
-#pragma unroll
-  for (int m = 0; m < M; ++m)
-#pragma unroll
-    for (int n = 0; n < M; ++n) {
-      const int r = tr + 16 * m, cc = tc + 16 * n;
-      a[m][n] = IDENT ? (r == cc ? 1.0 : 0.0) : (double)X[(int64_t)cc * B + r];
-    }
 #pragma unroll 1
   for (int q = 0; q < M; ++q) {
     const double *lq = ls[q & 1];  // rows 16q.. of L, pitch PP
@@ -254,14 +322,7 @@ __device__ __forceinline__ void trsm_tile(const T *__restrict__ L, T *__restrict
       double x[NB];
 #pragma unroll
       for (int j = 0; j < NB; j += 2) *(double2 *)&x[j] = *(const double2 *)&px[t * PP + j];
-#pragma unroll
-      for (int j = 0; j < NB; ++j) {
-        double sacc = x[j];
-#pragma unroll
-        for (int i = 0; i < j; ++i) sacc -= x[i] * lq[j * PP + i];
-        x[j] = sacc * rdl[16 * q + j];
-        __builtin_amdgcn_sched_barrier(0);
-      }
+      row_solve<NB, PP>(x, lq, rdl + 16 * q);
 #pragma unroll
       for (int j = 0; j < NB; j += 2) *(double2 *)&px[t * PP + j] = *(const double2 *)&x[j];
     }
