@@ -247,8 +247,8 @@ void chol_profile_reset(void);
 
 /* ---- tuning knobs (process-wide; set before factorising) ---------------
  * "panel_width"  : tiles per outer step whose Step-3 update is applied in
- *                  one pass (1..8; 0 = automatic: 4 when the matrix has at
- *                  least 64 tile rows, else 2; default 0).
+ *                  one pass (1..8; 0 = automatic: 8 from 192 tile rows,
+ *                  4 from 64, else 2; default 0).
  * "lookahead"    : 1 overlaps the next panel's Steps 1-2 with the current
  *                  trailing update on a second stream (default 1).
  * "super_tile"   : side, in tiles, of the groups the trailing-update grid

@@ -454,7 +454,7 @@ int chol_factor_ex(const double *A, int64_t n, int64_t lda, int precision,
   // panel width: tile columns per Step-3 pass over the far trailing matrix
   const int64_t pw_opt =
       (opts && opts->panel_width > 0) ? (int64_t)opts->panel_width : g_opt.panel_width.load();
-  const int64_t w = pw_opt > 0 ? pw_opt : (N >= 64 ? 4 : 2);
+  const int64_t w = pw_opt > 0 ? pw_opt : (N >= 192 ? 8 : (N >= 64 ? 4 : 2));
   const int S =
       (int)((opts && opts->super_tile > 0) ? (int64_t)opts->super_tile : g_opt.super_tile.load());
   const int fp16 = precision == CHOL_FP16_SCALED;
