@@ -37,14 +37,15 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 # Bytes moved between L2 and the memory fabric per launch of the bulk FP64
-# update (update_f64_kernel<0>) in the n = 32768 workload: two rocprofv3 --pmc
-# runs (FETCH_SIZE, WRITE_SIZE) over one factorisation, each scaled by what
-# the same counter reads for a plain 1 GiB copy (FETCH_SIZE x 2.0, WRITE_SIZE
-# x 1.0).  Valid only for the kernel source it was measured on; otherwise
-# reported as null.  Algorithmic bytes per launch (each C tile read and
-# written once, each panel tile read once): 2.835e9.
-TRAFFIC = {"update_hip_sha256_16": "1e405aab669cd4df", "n": 32768, "bytes_per_launch": 5.494e9,
-           "algorithmic_bytes_per_launch": 2.835e9,
+# update (update_f64_kernel<0>) in the n = 32768 workload (panel width 8, 30
+# launches per factorisation): two rocprofv3 --pmc runs (FETCH_SIZE,
+# WRITE_SIZE) over one factorisation, each scaled by what the same counter
+# reads for a plain 1 GiB copy (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0).  Valid
+# only for the kernel source it was measured on; otherwise reported as null.
+# Algorithmic bytes per launch (each C tile read and written once, each panel
+# tile read once): 2.790e9.
+TRAFFIC = {"update_hip_sha256_16": "465e48d50a422e68", "n": 32768, "bytes_per_launch": 7.902e9,
+           "algorithmic_bytes_per_launch": 2.790e9,
            "source": "profiles/update_f64_kernel_traffic_n32768.md"}
 
 METRIC = "Cholesky GFLOP/s (n^3/3) + time-to-1e-10 solve, FP64 vs mixed; p50/p99 latency"
