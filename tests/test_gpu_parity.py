@@ -166,7 +166,7 @@ def test_schedule_invariance_bitwise():
     A = dev(oracle.gp_assemble(X, 1.0, 1.0, 0.1))
     outs = []
     try:
-        for w, la in [(1, 0), (2, 1), (4, 1), (3, 0)]:
+        for w, la in [(1, 0), (2, 1), (4, 1), (3, 0), (8, 1), (6, 0)]:
             P.set_option("panel_width", w)
             P.set_option("lookahead", la)
             for prec in ("fp64", "fp32"):
@@ -289,6 +289,41 @@ def test_solve_bounded_wait_never_hangs():
     x = host(Bd)
     assert np.isfinite(x).all()
     assert np.linalg.norm(x - xref) / np.linalg.norm(xref) <= 1e-10
+
+
+def test_full_size_sampled_parity():
+    """The bench configuration (n = 32768, tile 128, automatic schedule: panel
+    width 8, lookahead) checked where the oracle can follow it: sampled
+    entries of L L^T against the oracle's A_ij, within the classical
+    componentwise bound (n+1)u/(1-(n+1)u) |L||L^T|; and the k = 1 solve through
+    the oracle's matrix-free residual and rigorous certificate."""
+    n = 32768
+    X, B = gp_inputs.gp_problem(n, seed=0, k=1)
+    hp = (1.0, 1.0, 0.1)
+    Ad = P.gp_assemble(torch.from_numpy(X).cuda(), *hp, full=False)
+    F = P.chol_factor(Ad, "fp64", 128)
+    assert F.info() == 0
+    Ld = P.chol_factor_to_dense(F)
+    rng = np.random.default_rng(7)
+    pairs = [(int(i), int(rng.integers(0, i + 1))) for i in rng.integers(0, n, size=48)]
+    pairs += [(n - 1, n - 1), (n - 1, 0), (128, 127), (0, 0)]
+    rows = sorted({r for pr in pairs for r in pr})
+    Lrows = {r: host(Ld[r, :]).astype(np.float64) for r in rows}
+    gam = (n + 1) * U / (1 - (n + 1) * U)
+    for i, j in pairs:
+        li, lj = Lrows[i][: j + 1], Lrows[j][: j + 1]
+        s = float(np.sum(li.astype(np.longdouble) * lj.astype(np.longdouble)))
+        a = oracle.gp_entry(X, i, j, *hp)
+        # plus the assembly difference (exp within a few ulp of the oracle's)
+        bound = gam * float(np.sum(np.abs(li) * np.abs(lj))) + 8 * U * abs(a)
+        assert abs(s - a) <= bound, (i, j, s, a, bound)
+    assert np.all(host(Ld[0, 1:64]) == 0.0)  # upper triangle written as zero
+    del Ld
+    Bd = dev(B)
+    P.chol_solve(F, Bd)
+    x = host(Bd)[:, 0]
+    r = oracle.gp_residual(X, *hp, x, B[:, 0])
+    assert oracle.certificate(r, x, hp[2]) <= 1e-10
 
 
 # ----------------------------------------------------------- edge cases ---
