@@ -18,6 +18,8 @@ numpy arrays to it.  Each function cites the passage it follows:
 * ``residual`` / ``gp_residual`` - b - A x with long-double accumulation.
 * ``refine``       - iterative refinement with a low-precision factor (the
   paper lists mixed precision as future work; textbook IR).
+* ``cg``           - the paper's conjugate gradient method (Fundamentals, "The
+  Conjugate Gradient method"), with its periodic true-residual recomputation.
 * ``pcg``          - CG (paper's CG algorithm) preconditioned with M = F F^T.
 * ``backward_error`` / ``certificate`` - checkers.
 """
@@ -71,6 +73,8 @@ def _load():
         lib.oracle_pcg.argtypes = [_D, _I, _D, _I, _I, _D, _D, _I, ctypes.c_double, ctypes.c_double,
                                    _I, _I, _IP, _D]
         lib.oracle_pcg.restype = ctypes.c_int64
+        lib.oracle_cg.argtypes = [_D, _I, _I, _D, _D, _I, ctypes.c_double, _I, _I, _IP, _D]
+        lib.oracle_cg.restype = ctypes.c_int64
         lib.oracle_backward_error.argtypes = [_D, _I, _D, _I, _I]
         lib.oracle_backward_error.restype = ctypes.c_double
         lib.oracle_certificate.argtypes = [_D, _D, _I, ctypes.c_double]
@@ -188,6 +192,19 @@ def pcg(F, A, B, lam: float, tol: float = 1e-10, max_iter: int = 200, recompute:
     failed = _load().oracle_pcg(_p(F), n, _p(A), n, n, _p(Bc), _p(X), k, lam, tol, max_iter, recompute,
                                 it.ctypes.data_as(_IP), _p(ce))
     return X, it, ce, int(failed)
+
+
+def cg(A, B, X0=None, eps: float = 1e-6, max_iter: int = 10000, recompute: int = 50):
+    """The paper's CG per column.  Returns (X, iters[k], relres[k], n_stopped)."""
+    A = np.asfortranarray(A, dtype=np.float64)
+    Bc = _colmajor(B)
+    n, k = Bc.shape
+    X = np.zeros((n, k), dtype=np.float64, order="F") if X0 is None else _colmajor(X0)
+    it = np.zeros(k, dtype=np.int64)
+    rr = np.zeros(k, dtype=np.float64)
+    stopped = _load().oracle_cg(_p(A), n, n, _p(Bc), _p(X), k, eps, max_iter, recompute,
+                                it.ctypes.data_as(_IP), _p(rr))
+    return X, it, rr, int(stopped)
 
 
 def backward_error(A, L) -> float:

@@ -311,6 +311,74 @@ int64_t oracle_pcg(const double *F, int64_t ldf, const double *A, int64_t lda,
 }
 
 /* ------------------------------------------------------------------------ */
+/* The paper's conjugate gradient method (Fundamentals section, "The         */
+/* Conjugate Gradient method", left column of its CG / Cholesky algorithm    */
+/* figure, after Shewchuk), one right-hand side at a time, x holding the     */
+/* starting guess on entry:                                                  */
+/*   s = r = b - A x;  u = u0 = r.r                                          */
+/*   while u > eps^2 u0 (and fewer than max_iter iterations):                */
+/*     t = A s;  alpha = u / s.t;  x += alpha s;                             */
+/*     r -= alpha t, except that every `recompute`-th iteration takes the    */
+/*       true residual r = b - A x instead (the paper's periodic             */
+/*       recomputation; recompute <= 0 never does);                          */
+/*     v = u;  u = r.r;  beta = u / v;  s = r + beta s                       */
+/* A full (n x n, lda).  Products and dots accumulate in long double.        */
+/* iters[c] = iterations taken, relres[c] = sqrt(u / u0) at exit (0 when     */
+/* b - A x0 = 0).  Returns the number of columns stopped by max_iter.        */
+/* ------------------------------------------------------------------------ */
+static void matvec(const double *A, int64_t lda, int64_t n, const double *v,
+                   double *out) {
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < n; ++i) {
+    long double t = 0.0L;
+    for (int64_t j = 0; j < n; ++j) t += (long double)AT(A, lda, i, j) * v[j];
+    out[i] = (double)t;
+  }
+}
+
+int64_t oracle_cg(const double *A, int64_t lda, int64_t n, const double *B,
+                  double *X, int64_t k, double eps, int64_t max_iter,
+                  int64_t recompute, int64_t *iters, double *relres) {
+  double *r = (double *)malloc((size_t)n * sizeof(double));
+  double *s = (double *)malloc((size_t)n * sizeof(double));
+  double *t = (double *)malloc((size_t)n * sizeof(double));
+  int64_t stopped = 0;
+  for (int64_t c = 0; c < k; ++c) {
+    double *x = X + (size_t)c * n;
+    const double *b = B + (size_t)c * n;
+    matvec(A, lda, n, x, t);
+    for (int64_t i = 0; i < n; ++i) r[i] = b[i] - t[i];
+    memcpy(s, r, (size_t)n * sizeof(double));
+    double u = dot_col(r, r, n);
+    const double u0 = u;
+    int64_t it = 0;
+    while (u > eps * eps * u0 && it < max_iter) {
+      matvec(A, lda, n, s, t);
+      const double alpha = u / dot_col(s, t, n);
+      for (int64_t i = 0; i < n; ++i) x[i] += alpha * s[i];
+      ++it;
+      if (recompute > 0 && it % recompute == 0) {
+        matvec(A, lda, n, x, t);
+        for (int64_t i = 0; i < n; ++i) r[i] = b[i] - t[i];
+      } else {
+        for (int64_t i = 0; i < n; ++i) r[i] -= alpha * t[i];
+      }
+      const double v = u;
+      u = dot_col(r, r, n);
+      const double beta = u / v;
+      for (int64_t i = 0; i < n; ++i) s[i] = r[i] + beta * s[i];
+    }
+    if (u > eps * eps * u0) ++stopped;
+    if (iters) iters[c] = it;
+    if (relres) relres[c] = u0 > 0.0 ? sqrt(u / u0) : 0.0;
+  }
+  free(r);
+  free(s);
+  free(t);
+  return stopped;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Checkers.                                                                 */
 /* backward error ||A - L L^T||_F / ||A||_F over the full symmetric matrix,  */
 /* with L lower (upper triangle ignored) and A's lower triangle mirrored.    */

@@ -270,3 +270,99 @@ def test_inputs_are_seeded():
     s = gp_inputs.serving_stream(duration_s=2.0, seed=0)
     assert len(s) > 100 and all(256 <= r.n <= 8192 and 1 <= r.k <= 64 for r in s)
     assert all(a.arrival < b.arrival for a, b in zip(s, s[1:]))
+
+
+# ------------------------------------------------- conjugate gradients ---
+
+def test_cg_shewchuk_two_by_two_hand_worked():
+    # A = [[3, 2], [2, 6]], b = [2, -8], x0 = 0 (Shewchuk's example system).
+    # By hand: r0 = b, u0 = 68, t = A r0 = [-10, -44], s.t = 332,
+    # alpha = 68/332 = 17/83, so x1 = (17/83) b = [34/83, -136/83]; CG ends
+    # at the exact solution [2, -2] after n = 2 steps.
+    A = np.array([[3.0, 2.0], [2.0, 6.0]])
+    b = np.array([2.0, -8.0])
+    x1, it1, _, stopped = oracle.cg(A, b, eps=1e-14, max_iter=1, recompute=0)
+    assert it1[0] == 1 and stopped == 1
+    np.testing.assert_allclose(x1[:, 0], [34.0 / 83.0, -136.0 / 83.0], rtol=4 * U, atol=0)
+    x2, it2, rr, stopped = oracle.cg(A, b, eps=1e-14, max_iter=10, recompute=0)
+    assert it2[0] == 2 and stopped == 0 and rr[0] <= 1e-14
+    np.testing.assert_allclose(x2[:, 0], [2.0, -2.0], rtol=8 * U, atol=8 * U)
+
+
+def test_cg_scaled_identity_one_step():
+    b = np.random.default_rng(0).standard_normal(50)
+    x, it, rr, stopped = oracle.cg(3.0 * np.eye(50), b, eps=1e-12)
+    assert it[0] == 1 and stopped == 0
+    np.testing.assert_allclose(x[:, 0], b / 3.0, rtol=4 * U, atol=0)
+
+
+def test_cg_finite_termination_with_three_eigenvalues():
+    # A with 3 distinct eigenvalues: the Krylov space is exhausted after 3 steps.
+    rng = np.random.default_rng(1)
+    Q, _ = np.linalg.qr(rng.standard_normal((60, 60)))
+    lam = np.array([1.0, 2.5, 7.0])[rng.integers(0, 3, 60)]
+    A = (Q * lam) @ Q.T
+    A = 0.5 * (A + A.T)
+    b = rng.standard_normal(60)
+    x, it, rr, stopped = oracle.cg(A, b, eps=1e-10, recompute=0)
+    assert stopped == 0 and it[0] == 3
+    xs = np.linalg.solve(A, b)
+    assert np.linalg.norm(x[:, 0] - xs) <= 1e-12 * np.linalg.norm(xs)
+
+
+def test_cg_error_a_norm_decreases():
+    # CG minimises the A-norm of the error over a growing Krylov space.
+    n = 120
+    X, B = gp_inputs.gp_problem(n, seed=21, k=1)
+    A = oracle.gp_assemble(X, 1.0, 1.0, 0.1)
+    xs = np.linalg.solve(A, B[:, 0])
+    prev = np.inf
+    for m in range(1, 12):
+        x, it, _, _ = oracle.cg(A, B, eps=1e-15, max_iter=m, recompute=0)
+        assert it[0] == m
+        e = x[:, 0] - xs
+        en = float(e @ A @ e)
+        assert en < prev
+        prev = en
+
+
+def test_cg_against_lapack_on_gp_matrix():
+    n = 300
+    X, B = gp_inputs.gp_problem(n, seed=22, k=3)
+    A = oracle.gp_assemble(X, 1.0, 1.0, 0.1)
+    x, it, rr, stopped = oracle.cg(A, B, eps=1e-12, recompute=50)
+    assert stopped == 0 and np.all(rr <= 1e-12)
+    xs = sla.solve(A, B, assume_a="pos")
+    # ||x - x*|| <= ||r|| / lambda_min, lambda_min >= noise = 0.1
+    for c in range(3):
+        bound = 1e-12 * np.linalg.norm(B[:, c]) / 0.1 * 1.01 + 1e-13 * np.linalg.norm(xs[:, c])
+        assert np.linalg.norm(x[:, c] - xs[:, c]) <= bound
+
+
+def test_cg_recompute_every_step_is_true_residual():
+    n = 150
+    X, B = gp_inputs.gp_problem(n, seed=23, k=1)
+    A = oracle.gp_assemble(X, 0.7, 1.0, 0.05)
+    for m in (1, 4, 9):
+        x, it, rr, _ = oracle.cg(A, B, eps=1e-15, max_iter=m, recompute=1)
+        true = np.linalg.norm(B[:, 0] - A @ x[:, 0]) / np.linalg.norm(B[:, 0])
+        assert abs(rr[0] - true) <= 1e-12 * max(true, 1e-3)
+
+
+def test_cg_stopping_rule_first_crossing():
+    n = 200
+    X, B = gp_inputs.gp_problem(n, seed=24, k=1)
+    A = oracle.gp_assemble(X, 1.0, 1.0, 0.1)
+    eps = 1e-3
+    x, it, rr, stopped = oracle.cg(A, B, eps=eps, recompute=0)
+    assert stopped == 0 and rr[0] <= eps
+    _, it1, rr1, stopped1 = oracle.cg(A, B, eps=eps, max_iter=int(it[0]) - 1, recompute=0)
+    assert stopped1 == 1 and rr1[0] > eps  # one iteration fewer is not enough
+
+
+def test_cg_starting_guess():
+    A = np.array([[3.0, 2.0], [2.0, 6.0]])
+    b = np.array([[2.0], [-8.0]])
+    x, it, rr, stopped = oracle.cg(A, b, X0=np.array([[2.0], [-2.0]]), eps=1e-6)
+    assert it[0] == 0 and rr[0] == 0.0 and stopped == 0
+    assert np.array_equal(x[:, 0], [2.0, -2.0])
