@@ -13,7 +13,10 @@ Other workloads (``--workload``) print the same kind of JSON line:
   fp64_n1024    the small latency case (tile 128), p50/p99 over many steps;
   mixed_n65536  FP64 vs FP32-factor + refinement, time to a certified 1e-10
                 solution of one right-hand side;
-  fp64_n65536   the FP64 factorisation at n = 65536.
+  fp64_n65536   the FP64 factorisation at n = 65536;
+  cg_n65536     the paper's CG against the Cholesky solver on the same
+                system (eps 1e-6), value = n^3/3 over the CG time to solution;
+  mixed_fp16_n131072, serve  (see bench_fp16, bench_serve).
 
 The roofline object is measured live: every launch of the bulk
 trailing-triangle update (the dominant kernel, update_f64_kernel<0> or
@@ -84,7 +87,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="fp64_n32768",
                     choices=["fp64_n32768", "fp64_n1024", "fp64_n65536", "mixed_n65536",
-                             "mixed_fp16_n131072", "serve"])
+                             "mixed_fp16_n131072", "serve", "cg_n65536"])
     ap.add_argument("--duration", type=float, default=10.0, help="serve: seconds of arrivals")
     ap.add_argument("--rate", type=float, default=200.0, help="serve: mean arrivals per second")
     ap.add_argument("--workers", type=int, default=8, help="serve: concurrent requests")
@@ -132,6 +135,8 @@ def main():
         return bench_serve(args)
     if wl == "mixed_fp16_n131072":
         return bench_fp16(args)
+    if wl == "cg_n65536":
+        return bench_cg(args)
     n = args.n or {"fp64_n32768": 32768, "fp64_n1024": 1024, "fp64_n65536": 65536, "mixed_n65536": 65536}[wl]
     tile = args.tile
     steps, warmup = args.steps, args.warmup
@@ -280,6 +285,118 @@ def main():
     out.update(extra)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_n)
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline_cg(n: int, eps: float):
+    """The oracle's CG (assembled A, long-double products) on the host."""
+    import gp_inputs
+    import oracle
+    X, B = gp_inputs.gp_problem(n, d=8, k=1, seed=0)
+    oracle.build()
+    t0 = time.perf_counter()
+    A = oracle.gp_assemble(X, *HP)
+    x, it, rr, stopped = oracle.cg(A, B, eps=eps, max_iter=100000, recompute=50)
+    dt = time.perf_counter() - t0
+    assert stopped == 0
+    return {"value": round(n ** 3 / 3 / dt / 1e9, 3), "unit": "GFLOP/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": f"oracle gp_assemble + CG (eps {eps:g}, recompute 50) at n={n}, SE d=8, ls=1 var=1 "
+                      f"noise=0.1, seed 0: {int(it[0])} iterations, {dt:.2f} s; "
+                      f"GFLOP/s-equivalent = n^3/3 / time"}
+
+
+def bench_cg(args):
+    """The paper's CG against its Cholesky solver on the same system (its
+    CG/Cholesky comparison: eps = 1e-6, no iteration cap, the Cholesky time
+    including the forward and back substitution): SE kernel d=8, lengthscale 1,
+    variance 1, noise 0.1, n = 65536, one right-hand side, seed 0.  A is
+    resident in HBM (column-major, lower triangle) before timing starts.
+    value = n^3/3 over the CG time to solution, the unit of the Cholesky
+    lines, so the two compare directly."""
+    import torch
+    import gp_inputs
+    import paper_2605_13209_amd as P
+    n = args.n or 65536
+    eps, recompute = 1e-6, 50
+    X, B = gp_inputs.gp_problem(n, d=8, k=1, seed=0)
+    Xd = torch.from_numpy(X).cuda()
+    Bd = P.to_colmajor(torch.from_numpy(B))
+    A = P.colmajor_empty(n, n)
+    P.gp_assemble(Xd, *HP, full=False, out=A)
+    ws = torch.empty(P.cg_workspace_bytes(n, 1, 128), dtype=torch.uint8, device="cuda")
+    Xs = P.colmajor_empty(n, 1)
+    steps, warmup = args.steps, args.warmup
+    if steps == 5:
+        steps = 3
+    t_cg, its, rrs = [], [], []
+    for rep in range(warmup + steps):
+        Xs.zero_()
+        torch.cuda.synchronize()
+        if rep == warmup and not args.no_profile:
+            P.chol_profile_reset()
+            P.set_option("profile", 2)
+        t0 = time.perf_counter()
+        res = P.cg_solve(A, Bd, X=Xs, eps=eps, max_iter=100000, recompute=recompute, tile=128, workspace=ws)
+        t1 = time.perf_counter()
+        if not res.converged:
+            raise RuntimeError(f"CG did not converge: {res}")
+        if rep >= warmup:
+            t_cg.append((t1 - t0) * 1e3)
+            its.append(res.iters[0])
+            rrs.append(res.relres[0])
+    P.set_option("profile", 0)
+    kms, kl, kbytes = P.chol_profile_read()
+    R = P.chol_residual(A, Xs, Bd)
+    true_rel = float(torch.linalg.norm(R) / torch.linalg.norm(Bd))
+    del ws
+    torch.cuda.empty_cache()
+
+    # the Cholesky solver on the same system: FP64 factor + forward/back substitution
+    wsf = torch.empty(P.chol_factor_bytes(n, "fp64", 128), dtype=torch.uint8, device="cuda")
+    b1 = P.colmajor_empty(n, 1)
+    t_ch = []
+    for rep in range(1 + max(1, steps // 2)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        F = P.chol_factor(A, "fp64", 128, workspace=wsf, sync=False)
+        b1.copy_(Bd)
+        P.chol_solve(F, b1)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        if rep >= 1:
+            t_ch.append((t1 - t0) * 1e3)
+        if F.info() != 0:
+            raise RuntimeError("factorisation failed")
+    Rc = P.chol_residual(A, b1, Bd)
+    chol_rel = float(torch.linalg.norm(Rc) / torch.linalg.norm(Bd))
+
+    ms = float(np.mean(t_cg))
+    flops = n ** 3 / 3
+    roofline = None
+    if kl > 0 and kms > 0:
+        ach = kbytes / (kms * 1e-3) / 1e9
+        roofline = {"bound": "hbm", "achieved": round(ach, 1), "peak": 8000.0, "unit": "GB/s",
+                    "frac": round(ach / 8000.0, 4), "traffic": None,
+                    "kernel": "symv_tiles_kernel<128> (both products of every stored tile, one pass over "
+                              "the packed lower triangle)",
+                    "launches": kl, "avg_launch_us": round(kms * 1e3 / kl, 2),
+                    "algorithmic_bytes_per_launch": round(kbytes / kl)}
+    out = {"metric": METRIC, "value": round(flops / (ms * 1e-3) / 1e9, 2), "unit": "GFLOP/s", "n_gpus": 1,
+           "steps": steps, "warmup": warmup, "ms_per_step": round(ms, 3), "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": f"cg_vs_cholesky_n{n}", "n": n, "tile": 128, "rhs": 1, "eps": eps,
+                      "recompute": recompute, "kernel": "SE d=8 lengthscale=1 variance=1 noise=0.1",
+                      "seed": 0, "value_is": "n^3/3 / CG time to solution"},
+           "roofline": roofline,
+           "cg": {"time_to_solution_ms": round(ms, 2), "p50_ms": round(percentile(t_cg, 50), 2),
+                  "p99_ms": round(percentile(t_cg, 99), 2), "iterations": int(max(its)),
+                  "ms_per_iteration": round(ms / max(its), 4), "relres_recurrence": float(max(rrs)),
+                  "relres_true": true_rel},
+           "cholesky": {"time_to_solution_ms": round(float(np.mean(t_ch)), 2), "relres_true": chol_rel},
+           "speedup_cg_vs_cholesky": round(float(np.mean(t_ch)) / ms, 3)}
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline_cg(args.cpu_n if args.cpu_n != 8192 else 4096, eps)
     print(json.dumps(out), flush=True)
 
 

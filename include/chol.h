@@ -241,7 +241,10 @@ const char *chol_status_string(int status);
  * inner dimension of the launch).  chol_profile_read waits for the recorded
  * events and returns the summed kernel time (ms), the number of launches and
  * the summed flops; chol_profile_reset forgets everything recorded.  Not
- * thread-safe; meant for benchmarks.                                       */
+ * thread-safe; meant for benchmarks.  cg_solve's tile-product launches are
+ * recorded the same way (with either value of "profile"), their work being
+ * bytes, not flops: 8 b^2 per stored tile (the packed triangle read once).
+ * Read the records of one kind of call at a time.                          */
 int chol_profile_read(double *ms, int64_t *launches, double *flops);
 void chol_profile_reset(void);
 
@@ -270,6 +273,45 @@ void chol_profile_reset(void);
  * Returns CHOL_OK or -1 (unknown key) / -2 (value out of range).         */
 int chol_set_option(const char *key, int64_t value);
 int64_t chol_get_option(const char *key);
+
+/* ---- conjugate gradients (the paper's iterative solver) ----------------
+ * The CG method of the paper (Fundamentals, "The Conjugate Gradient
+ * method", and the left column of its CG / Cholesky algorithm figure), for
+ * up to CG_MAX_RHS right-hand sides at once, each column with its own
+ * scalars and its own stopping test:
+ *   s = r = b - A x;  u = u0 = r.r
+ *   while u > eps^2 u0 and fewer than max_iter iterations:
+ *     t = A s;  alpha = u / s.t;  x += alpha s;
+ *     r -= alpha t, except every `recompute`-th iteration, which takes the
+ *       true residual r = b - A x (the paper's periodic recomputation;
+ *       0 = never);
+ *     v = u;  u = r.r;  beta = u / v;  s = r + beta s.
+ * A is stored as in the paper's implementation: only the diagonal and lower
+ * tiles (tile side `tile`, 64 or 128, 0 = 128), packed into the workspace
+ * from the lower triangle of the caller's column-major A (lda >= n) at the
+ * start of the call; each iteration reads that packed triangle once.
+ * B (n x nrhs, ldb >= n) is read; X (n x nrhs, ldx >= n) holds the starting
+ * guess on entry (zeros for the usual start) and the final iterate on exit.
+ * The workspace (device, 256-byte aligned, ws_bytes >= cg_workspace_bytes)
+ * holds the packed tiles, partial products, the vectors and the scalars.
+ * iters (host, nrhs entries, may be NULL) receives the iterations taken per
+ * column, relres (host, nrhs, may be NULL) sqrt(u / u0) at exit (0 if
+ * b - A x0 = 0).
+ * Synchronous: returns after the iteration has finished (the host checks the
+ * columns' stopping flags one iteration behind the device, so at most one
+ * extra iteration is enqueued, and it leaves finished columns unchanged).
+ * Returns CHOL_OK when every column met its test, CHOL_ERR_NOT_CONVERGED
+ * when some column stopped at max_iter (X still holds its iterate), -i for
+ * an invalid argument i (1 <= nrhs <= CG_MAX_RHS, eps >= 0, max_iter >= 0,
+ * recompute >= 0), CHOL_ERR_WORKSPACE, CHOL_ERR_UNSUPPORTED (tile) or
+ * CHOL_ERR_HIP.  A that is not positive definite gives NaN or a
+ * non-converged result; it is not detected otherwise.                     */
+#define CG_MAX_RHS 16
+size_t cg_workspace_bytes(int64_t n, int tile, int64_t nrhs);
+int cg_solve(const double *A, int64_t n, int64_t lda, int tile, const double *B, int64_t ldb,
+             double *X, int64_t ldx, int64_t nrhs, double eps, int64_t max_iter,
+             int64_t recompute, void *workspace, size_t ws_bytes, int64_t *iters,
+             double *relres, void *stream);
 
 #ifdef __cplusplus
 }

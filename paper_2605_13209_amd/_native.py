@@ -21,6 +21,7 @@ CHOL_FP64, CHOL_FP32, CHOL_FP16_SCALED = 0, 1, 2
 PRECISIONS = {"fp64": CHOL_FP64, "fp32": CHOL_FP32, "fp16_scaled": CHOL_FP16_SCALED}
 CHOL_REFINE_IR, CHOL_REFINE_PCG = 0, 1
 METHODS = {"ir": CHOL_REFINE_IR, "pcg": CHOL_REFINE_PCG}
+CHOL_ERR_WORKSPACE = -101
 CHOL_ERR_NOT_CONVERGED = -102
 CHOL_ERR_NOT_SPD = -103
 
@@ -70,7 +71,11 @@ EXPORTS = {
     "chol_get_option": (_i64, [ctypes.c_char_p]),
     "chol_profile_read": (_int, [ctypes.POINTER(_dbl), ctypes.POINTER(_i64), ctypes.POINTER(_dbl)]),
     "chol_profile_reset": (None, []),
+    "cg_workspace_bytes": (_sz, [_i64, _int, _i64]),
+    "cg_solve": (_int, [_vp, _i64, _i64, _int, _vp, _i64, _vp, _i64, _i64, _dbl, _i64, _i64, _vp, _sz,
+                        ctypes.POINTER(_i64), ctypes.POINTER(_dbl), _vp]),
 }
+CG_MAX_RHS = 16
 
 
 def lib():
@@ -306,3 +311,42 @@ def chol_factor_to_dense(F: Factor, out: torch.Tensor | None = None, stream=None
     L = colmajor_empty(F.n, F.n, device=F.workspace.device) if out is None else out
     _check(lib().chol_factor_to_dense(F.handle, L.data_ptr(), _ld(L), _stream(stream)), "chol_factor_to_dense")
     return L
+
+
+def cg_workspace_bytes(n: int, nrhs: int = 1, tile: int = 0) -> int:
+    return int(lib().cg_workspace_bytes(int(n), int(tile), int(nrhs)))
+
+
+@dataclass
+class CgResult:
+    X: torch.Tensor
+    iters: list
+    relres: list
+    converged: bool
+    status: int
+
+
+def cg_solve(A: torch.Tensor, B: torch.Tensor, X: torch.Tensor | None = None, *, eps: float = 1e-6,
+             max_iter: int = 100000, recompute: int = 50, tile: int = 0, workspace: torch.Tensor | None = None,
+             raise_on_fail: bool = False, stream=None) -> CgResult:
+    """The paper's CG on the GPU (cg_solve): X holds the starting guess (zeros
+    if None) and receives the iterate; synchronous."""
+    _need_device(A, "A")
+    _need_device(B, "B")
+    n, k = B.shape
+    if X is None:
+        X = colmajor_empty(n, k, device=B.device)
+        X.zero_()
+    need = cg_workspace_bytes(n, k, tile)
+    if need == 0:
+        raise ValueError("invalid n / nrhs / tile")
+    if workspace is None:
+        workspace = torch.empty(need, dtype=torch.uint8, device=B.device)
+    its = (_i64 * k)()
+    rr = (_dbl * k)()
+    rc = lib().cg_solve(A.data_ptr(), n, _ld(A), int(tile), B.data_ptr(), _ld(B), X.data_ptr(), _ld(X), k,
+                        float(eps), int(max_iter), int(recompute), workspace.data_ptr(),
+                        workspace.numel() * workspace.element_size(), its, rr, _stream(stream))
+    if rc not in (0, CHOL_ERR_NOT_CONVERGED) or (rc != 0 and raise_on_fail):
+        _check(rc, "cg_solve")
+    return CgResult(X, [int(v) for v in its], [float(v) for v in rr], rc == 0, rc)

@@ -170,6 +170,29 @@ void update(void *tiles, int st, int b, int64_t N, int64_t p0, int pw, int64_t k
   if (a && e) g_prof.push_back({a, e, update_flops(b, N, pw, k0, k1, mode)});
 }
 
+}  // namespace
+
+// Event brackets for kernels launched by other entry points (the CG tile
+// product): recorded into the same list as the trailing-update launches,
+// with `work` in that kernel's own unit.
+namespace chol {
+int64_t profile_option() { return g_opt.profile.load(); }
+hipEvent_t profile_begin(hipStream_t s) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  hipEvent_t a = prof_event();
+  if (a) (void)hipEventRecord(a, s);
+  return a;
+}
+void profile_end(hipStream_t s, hipEvent_t a, double work) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  hipEvent_t e = prof_event();
+  if (e) (void)hipEventRecord(e, s);
+  if (a && e) g_prof.push_back({a, e, work});
+}
+}  // namespace chol
+
+namespace {
+
 int store_of(int precision) { return precision == CHOL_FP64 ? STORE_F64 : STORE_F32; }
 size_t esize_of(int precision) { return precision == CHOL_FP64 ? 8 : 4; }
 bool tile_ok(int tile) { return tile == 64 || tile == 128; }

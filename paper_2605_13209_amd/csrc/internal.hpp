@@ -102,4 +102,35 @@ void launch_axpby(const double *x, int64_t ldx, double *y, int64_t ldy, int64_t 
 void launch_copy(const double *x, int64_t ldx, double *y, int64_t ldy, int64_t n,
                  int64_t nrhs, hipStream_t s);
 
+// Kernel timing hooks (option "profile"): profile_begin records an event
+// on s before a launch, profile_end one after it and files the pair with the
+// launch's algorithmic work for chol_profile_read.
+int64_t profile_option();
+hipEvent_t profile_begin(hipStream_t s);
+void profile_end(hipStream_t s, hipEvent_t a, double work);
+
+// ---- conjugate gradients on the packed lower tiles (FP64) ----------------
+// Partial products of every stored tile with v (K columns, ldv): part holds
+// tile_count(N) * 2 * K * b doubles.
+void launch_cg_symv(const double *tiles, int b, int64_t N, const double *v, int64_t ldv, int K,
+                    double *part, hipStream_t s);
+// Row sums of the partials; mode 0: t = A s and s.t partials, 1: r = b - A x
+// for active columns and r.r partials, 2: r = s = b - A x and r.r partials.
+enum { CG_RED_T = 0, CG_RED_RESID = 1, CG_RED_INIT = 2 };
+void launch_cg_reduce(const double *part, int b, int64_t N, int K, int mode, double *t, double *sv,
+                      double *r, const double *bv, int64_t ld, const int *act, double *pdot,
+                      hipStream_t s);
+void launch_cg_xr(int b, int64_t N, int K, const double *pdot, const double *u_in, const int *act,
+                  double *x, double *r, const double *sv, const double *t, int64_t ld,
+                  int recompute_now, double *prr, hipStream_t s);
+void launch_cg_s(int b, int64_t N, int K, const double *prr, const double *u_in, const int *act_in,
+                 double *u_out, int *act_out, const double *u0, double eps2, int *iters,
+                 const double *r, double *sv, int64_t ld, hipStream_t s);
+void launch_cg_init(int b, int64_t N, int K, const double *prr, double *u, double *u0, int *act,
+                    int *iters, double eps2, hipStream_t s);
+void launch_cg_copy_in(const double *src, int64_t lds, int64_t n, int64_t n_pad, int K, double *dst,
+                       int64_t ld, hipStream_t s);
+void launch_cg_copy_out(const double *src, int64_t ld, int64_t n, int K, double *dst, int64_t ldd,
+                        hipStream_t s);
+
 }  // namespace chol

@@ -90,3 +90,18 @@ def test_product_path_fails_loudly_without_library(monkeypatch):
     monkeypatch.setattr(_native, "LIB_PATH", "/nonexistent/libchol_mi355x.so")
     with pytest.raises(RuntimeError, match="not built"):
         _native.lib()
+
+
+def test_cg_workspace_bytes():
+    def al(x):
+        return (x + 255) // 256 * 256
+    n, b, k = 1000, 128, 3
+    N = 8
+    T = N * (N + 1) // 2
+    want = al(T * b * b * 8) + al(T * 2 * k * b * 8) + al(5 * N * b * k * 8) + 2 * al(N * k * 8) \
+        + al(3 * 16 * 8 + 3 * 16 * 4)
+    assert P.cg_workspace_bytes(n, k, 128) == want
+    assert P.cg_workspace_bytes(n, k, 0) == want
+    assert P.cg_workspace_bytes(n, 17) == 0 and P.cg_workspace_bytes(n, 0) == 0
+    assert P.cg_workspace_bytes(n, 1, 96) == 0
+    assert P.cg_workspace_bytes(0, 1) == al(3 * 16 * 8 + 3 * 16 * 4)
