@@ -51,6 +51,11 @@ TRAFFIC = {"update_hip_sha256_16": "465e48d50a422e68", "n": 32768, "bytes_per_la
            "algorithmic_bytes_per_launch": 2.790e9,
            "source": "profiles/update_f64_kernel_traffic_n32768.md"}
 
+# The same for the CG tile product (symv_tiles_kernel<128>) at n = 65536:
+# FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 per launch.
+CG_TRAFFIC = {"cg_hip_sha256_16": "6793051c70b70a14", "n": 65536, "bytes_per_launch": 17.49e9,
+              "source": "profiles/symv_tiles_kernel_cg_n65536.md"}
+
 METRIC = "Cholesky GFLOP/s (n^3/3) + time-to-1e-10 solve, FP64 vs mixed; p50/p99 latency"
 FP64_PEAK_TFLOPS = 78.6   # MI355X dense FP64 matrix peak
 FP32_PEAK_TFLOPS = 157.3  # MI355X dense FP32 matrix peak
@@ -99,6 +104,9 @@ def main():
     ap.add_argument("--cpu-n", type=int, default=8192)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
+    ap.add_argument("--cg-max-iter", type=int, default=0,
+                    help="cg_n65536: cap the CG iterations (profiling runs; 0 = run to eps)")
+    ap.add_argument("--no-cholesky", action="store_true", help="cg_n65536: skip the Cholesky comparison")
     ap.add_argument("--copy-probe-gib", type=float, default=0.0,
                     help="before the workload, one plain device copy of this many GiB (outside the "
                          "timed region): the known-size kernel that calibrates byte counters")
@@ -337,9 +345,10 @@ def bench_cg(args):
             P.chol_profile_reset()
             P.set_option("profile", 2)
         t0 = time.perf_counter()
-        res = P.cg_solve(A, Bd, X=Xs, eps=eps, max_iter=100000, recompute=recompute, tile=128, workspace=ws)
+        res = P.cg_solve(A, Bd, X=Xs, eps=eps, max_iter=args.cg_max_iter or 100000, recompute=recompute,
+                         tile=128, workspace=ws)
         t1 = time.perf_counter()
-        if not res.converged:
+        if not res.converged and not args.cg_max_iter:
             raise RuntimeError(f"CG did not converge: {res}")
         if rep >= warmup:
             t_cg.append((t1 - t0) * 1e3)
@@ -356,7 +365,7 @@ def bench_cg(args):
     wsf = torch.empty(P.chol_factor_bytes(n, "fp64", 128), dtype=torch.uint8, device="cuda")
     b1 = P.colmajor_empty(n, 1)
     t_ch = []
-    for rep in range(1 + max(1, steps // 2)):
+    for rep in range(0 if args.no_cholesky else 1 + max(1, steps // 2)):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         F = P.chol_factor(A, "fp64", 128, workspace=wsf, sync=False)
@@ -368,8 +377,10 @@ def bench_cg(args):
             t_ch.append((t1 - t0) * 1e3)
         if F.info() != 0:
             raise RuntimeError("factorisation failed")
-    Rc = P.chol_residual(A, b1, Bd)
-    chol_rel = float(torch.linalg.norm(Rc) / torch.linalg.norm(Bd))
+    chol_rel = None
+    if t_ch:
+        Rc = P.chol_residual(A, b1, Bd)
+        chol_rel = float(torch.linalg.norm(Rc) / torch.linalg.norm(Bd))
 
     ms = float(np.mean(t_cg))
     flops = n ** 3 / 3
@@ -377,7 +388,8 @@ def bench_cg(args):
     if kl > 0 and kms > 0:
         ach = kbytes / (kms * 1e-3) / 1e9
         roofline = {"bound": "hbm", "achieved": round(ach, 1), "peak": 8000.0, "unit": "GB/s",
-                    "frac": round(ach / 8000.0, 4), "traffic": None,
+                    "frac": round(ach / 8000.0, 4), "traffic": measured_cg_traffic(n),
+                    "traffic_unit": "bytes per launch between L2 and the memory fabric (calibrated counters)",
                     "kernel": "symv_tiles_kernel<128> (both products of every stored tile, one pass over "
                               "the packed lower triangle)",
                     "launches": kl, "avg_launch_us": round(kms * 1e3 / kl, 2),
@@ -393,8 +405,9 @@ def bench_cg(args):
                   "p99_ms": round(percentile(t_cg, 99), 2), "iterations": int(max(its)),
                   "ms_per_iteration": round(ms / max(its), 4), "relres_recurrence": float(max(rrs)),
                   "relres_true": true_rel},
-           "cholesky": {"time_to_solution_ms": round(float(np.mean(t_ch)), 2), "relres_true": chol_rel},
-           "speedup_cg_vs_cholesky": round(float(np.mean(t_ch)) / ms, 3)}
+           "cholesky": {"time_to_solution_ms": round(float(np.mean(t_ch)), 2) if t_ch else None,
+                        "relres_true": chol_rel},
+           "speedup_cg_vs_cholesky": round(float(np.mean(t_ch)) / ms, 3) if t_ch else None}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline_cg(args.cpu_n if args.cpu_n != 8192 else 4096, eps)
     print(json.dumps(out), flush=True)
@@ -483,6 +496,20 @@ def measured_traffic(n: int, dtype: str):
     if dtype != "f64" or n != TRAFFIC["n"] or h != TRAFFIC["update_hip_sha256_16"]:
         return None
     return TRAFFIC["bytes_per_launch"]
+
+
+def measured_cg_traffic(n: int):
+    """Counter-measured bytes per CG tile-product launch, or None when the
+    order or the kernel source differs from the one the counters saw."""
+    import hashlib
+    src = os.path.join(ROOT, "paper_2605_13209_amd", "csrc", "cg.hip")
+    try:
+        h = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    except OSError:
+        return None
+    if n != CG_TRAFFIC["n"] or h != CG_TRAFFIC["cg_hip_sha256_16"]:
+        return None
+    return CG_TRAFFIC["bytes_per_launch"]
 
 
 def bench_serve(args):
