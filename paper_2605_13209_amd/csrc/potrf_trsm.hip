@@ -27,11 +27,15 @@ __device__ inline double readlane_f64(double v, int l) {
 // scaled and then subtracted from the later x_i (the same operations in the
 // same order as the row-wise substitution), column j + 1 of L being read
 // while column j is applied.
-template <int NB, int PP>
+// LEAN reads each reciprocal diagonal entry when it is used instead of all
+// of them up front (fewer registers live at once).
+template <int NB, int PP, bool LEAN = false>
 __device__ __forceinline__ void row_solve(double (&x)[NB], const double *l, const double *rdv) {
   double rv[NB], col[2][NB];
+  if (!LEAN) {
 #pragma unroll
-  for (int j = 0; j < NB; ++j) rv[j] = rdv[j];
+    for (int j = 0; j < NB; ++j) rv[j] = rdv[j];
+  }
 #pragma unroll
   for (int i = 1; i < NB; ++i) col[0][i] = l[i * PP];
 #pragma unroll
@@ -40,7 +44,7 @@ __device__ __forceinline__ void row_solve(double (&x)[NB], const double *l, cons
 #pragma unroll
       for (int i = j + 2; i < NB; ++i) col[(j + 1) & 1][i] = l[i * PP + j + 1];
     }
-    x[j] *= rv[j];
+    x[j] *= LEAN ? rdv[j] : rv[j];
 #pragma unroll
     for (int i = j + 1; i < NB; ++i) x[i] -= x[j] * col[j & 1][i];
     __builtin_amdgcn_sched_barrier(0);
@@ -312,7 +316,6 @@ __device__ __forceinline__ void trsm_tile(const T *__restrict__ L, T *__restrict
   for (int q = 0; q < M; ++q) {
     const double *lq = ls[q & 1];  // rows 16q.. of L, pitch PP
     double nxt[PF];
-    if (q + 1 < M) lget(q + 1, nxt);
     // (1) block q of X to LDS
 #pragma unroll
     for (int m = 0; m < M; ++m) px[(tr + 16 * m) * PP + tc] = a[m][0];
@@ -322,11 +325,13 @@ __device__ __forceinline__ void trsm_tile(const T *__restrict__ L, T *__restrict
       double x[NB];
 #pragma unroll
       for (int j = 0; j < NB; j += 2) *(double2 *)&x[j] = *(const double2 *)&px[t * PP + j];
-      row_solve<NB, PP>(x, lq, rdl + 16 * q);
+      row_solve<NB, PP, true>(x, lq, rdl + 16 * q);
 #pragma unroll
       for (int j = 0; j < NB; j += 2) *(double2 *)&px[t * PP + j] = *(const double2 *)&x[j];
     }
     __syncthreads();
+    // the next column block of L is loaded while this block is applied
+    if (q + 1 < M) lget(q + 1, nxt);
     // (3) the solved block to HBM; update of the remaining columns
     for (int e = t; e < B * NB; e += 256) {
       const int r = e % B, u = e / B;
