@@ -21,7 +21,8 @@ numpy arrays to it.  Each function cites the passage it follows:
 * ``cg``           - the paper's conjugate gradient method (Fundamentals, "The
   Conjugate Gradient method"), with its periodic true-residual recomputation.
 * ``pcg``          - CG (paper's CG algorithm) preconditioned with M = F F^T.
-* ``backward_error`` / ``certificate`` - checkers.
+* ``backward_error`` / ``backward_error_estimate`` / ``certificate`` -
+  checkers (the estimate is Hutchinson's, for orders the exact one cannot reach).
 """
 from __future__ import annotations
 
@@ -75,6 +76,8 @@ def _load():
         lib.oracle_pcg.restype = ctypes.c_int64
         lib.oracle_cg.argtypes = [_D, _I, _I, _D, _D, _I, ctypes.c_double, _I, _I, _IP, _D]
         lib.oracle_cg.restype = ctypes.c_int64
+        lib.oracle_backward_error_probes.argtypes = [_D, _I, _D, _I, ctypes.c_double, ctypes.c_double,
+                                                     ctypes.c_double, _D, _I, _I, _D, _I, _D, _D]
         lib.oracle_backward_error.argtypes = [_D, _I, _D, _I, _I]
         lib.oracle_backward_error.restype = ctypes.c_double
         lib.oracle_certificate.argtypes = [_D, _D, _I, ctypes.c_double]
@@ -212,6 +215,26 @@ def backward_error(A, L) -> float:
     L = np.asfortranarray(L, dtype=np.float64)
     n = A.shape[0]
     return _load().oracle_backward_error(_p(A), n, _p(L), n, n)
+
+
+def backward_error_estimate(L, Z, A=None, Xfeat=None, lengthscale=1.0, variance=1.0, noise=0.0):
+    """Hutchinson estimate of ||A - L L^T||_F / ||A||_F from the probe columns
+    Z; A dense, or (A None) the GP matrix of the features Xfeat, matrix-free.
+    Returns (estimate, num, den)."""
+    L = np.asfortranarray(L, dtype=np.float64)
+    n = L.shape[0]
+    Zc = _colmajor(Z)
+    k = Zc.shape[1]
+    num, den = ctypes.c_double(0), ctypes.c_double(0)
+    if A is not None:
+        A = np.asfortranarray(A, dtype=np.float64)
+        a_ptr, lda, f_ptr, d = _p(A), n, None, 0
+    else:
+        Xfeat = np.ascontiguousarray(Xfeat, dtype=np.float64)
+        a_ptr, lda, f_ptr, d = None, 1, _p(Xfeat), Xfeat.shape[1]
+    _load().oracle_backward_error_probes(a_ptr, lda, f_ptr, d, lengthscale, variance, noise, _p(L), L.shape[0],
+                                         n, _p(Zc), k, ctypes.byref(num), ctypes.byref(den))
+    return float(np.sqrt(num.value / den.value)), num.value, den.value
 
 
 def certificate(r, x, lam: float) -> float:

@@ -402,6 +402,62 @@ double oracle_backward_error(const double *A, int64_t lda, const double *L,
   return (double)sqrtl(num / den);
 }
 
+/* Randomized backward-error estimate for orders where the exact checker is */
+/* too slow (Hutchinson's trace estimator): for probe vectors z ~ N(0, I),  */
+/* E[||E z||^2] = ||E||_F^2 with E = A - L L^T.  For the k probes Z (n x k, */
+/* column-major) this returns num = sum_p ||A z_p - L (L^T z_p)||^2 and     */
+/* den = sum_p ||A z_p||^2, so sqrt(num / den) estimates ||E||_F / ||A||_F.  */
+/* A is dense (lda) or, with A == NULL, the GP matrix of O1 from features F */
+/* (n x d row-major), each entry computed once for all probes.  L lower,    */
+/* column-major (ldl), upper triangle ignored.  Long-double accumulation.   */
+void oracle_backward_error_probes(const double *A, int64_t lda, const double *F,
+                                  int64_t d, double ls, double var, double noise,
+                                  const double *L, int64_t ldl, int64_t n,
+                                  const double *Z, int64_t k, double *num,
+                                  double *den) {
+  long double *W = (long double *)calloc((size_t)n * k, sizeof(long double));
+  long double *Y = (long double *)calloc((size_t)n * k, sizeof(long double));
+  long double *AZ = (long double *)calloc((size_t)n * k, sizeof(long double));
+  /* W = L^T Z: W_j = sum_{i >= j} L_ij z_i */
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int64_t j = 0; j < n; ++j)
+    for (int64_t p = 0; p < k; ++p) {
+      long double t = 0.0L;
+      for (int64_t i = j; i < n; ++i)
+        t += (long double)AT(L, ldl, i, j) * Z[(size_t)p * n + i];
+      W[(size_t)p * n + j] = t;
+    }
+  /* Y = L W: Y_i = sum_{j <= i} L_ij W_j, by row blocks walking columns */
+  const int64_t RB = 64;
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int64_t r0 = 0; r0 < n; r0 += RB) {
+    const int64_t r1 = r0 + RB < n ? r0 + RB : n;
+    for (int64_t j = 0; j < r1; ++j)
+      for (int64_t i = (j > r0 ? j : r0); i < r1; ++i)
+        for (int64_t p = 0; p < k; ++p)
+          Y[(size_t)p * n + i] += (long double)AT(L, ldl, i, j) * W[(size_t)p * n + j];
+  }
+  /* A Z, each A_ij used for every probe */
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int64_t i = 0; i < n; ++i)
+    for (int64_t j = 0; j < n; ++j) {
+      const long double a = A ? (long double)AT(A, lda, (i > j ? i : j), (i > j ? j : i))
+                              : (long double)oracle_gp_entry(F, d, i, j, ls, var, noise);
+      for (int64_t p = 0; p < k; ++p) AZ[(size_t)p * n + i] += a * Z[(size_t)p * n + j];
+    }
+  long double nu = 0.0L, de = 0.0L;
+  for (size_t e = 0; e < (size_t)n * k; ++e) {
+    const long double r = AZ[e] - Y[e];
+    nu += r * r;
+    de += AZ[e] * AZ[e];
+  }
+  *num = (double)nu;
+  *den = (double)de;
+  free(W);
+  free(Y);
+  free(AZ);
+}
+
 /* Certificate cert = ||b - A x||_2 / (lam ||x||_2) for one column, given    */
 /* its residual; lam a lower bound on lambda_min(A).                         */
 double oracle_certificate(const double *r, const double *x, int64_t n,

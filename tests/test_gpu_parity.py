@@ -295,8 +295,9 @@ def test_full_size_sampled_parity():
     """The bench configuration (n = 32768, tile 128, automatic schedule: panel
     width 8, lookahead) checked where the oracle can follow it: sampled
     entries of L L^T against the oracle's A_ij, within the classical
-    componentwise bound (n+1)u/(1-(n+1)u) |L||L^T|; and the k = 1 solve through
-    the oracle's matrix-free residual and rigorous certificate."""
+    componentwise bound (n+1)u/(1-(n+1)u) |L||L^T|; the backward error of the
+    whole factor by the oracle's randomized estimate (<= 1e-12); and the k = 1
+    solve through the oracle's matrix-free residual and rigorous certificate."""
     n = 32768
     X, B = gp_inputs.gp_problem(n, seed=0, k=1)
     hp = (1.0, 1.0, 0.1)
@@ -318,7 +319,13 @@ def test_full_size_sampled_parity():
         bound = gam * float(np.sum(np.abs(li) * np.abs(lj))) + 8 * U * abs(a)
         assert abs(s - a) <= bound, (i, j, s, a, bound)
     assert np.all(host(Ld[0, 1:64]) == 0.0)  # upper triangle written as zero
-    del Ld
+    # the whole factor: Hutchinson estimate of ||A - L L^T||_F / ||A||_F with
+    # A matrix-free from the features (4 Gaussian probes, long double)
+    Lh = host(Ld)
+    Z = np.random.default_rng(11).standard_normal((n, 4))
+    est, _, _ = oracle.backward_error_estimate(Lh, Z, Xfeat=X, lengthscale=hp[0], variance=hp[1], noise=hp[2])
+    assert est <= 1e-12, est
+    del Ld, Lh
     Bd = dev(B)
     P.chol_solve(F, Bd)
     x = host(Bd)[:, 0]

@@ -366,3 +366,38 @@ def test_cg_starting_guess():
     x, it, rr, stopped = oracle.cg(A, b, X0=np.array([[2.0], [-2.0]]), eps=1e-6)
     assert it[0] == 0 and rr[0] == 0.0 and stopped == 0
     assert np.array_equal(x[:, 0], [2.0, -2.0])
+
+
+# ------------------------------------------- randomized backward error ---
+
+def test_backward_error_estimate_probe_values_brute_force():
+    # each probe's ||E z||^2 against E = A - L L^T formed explicitly (numpy)
+    n = 90
+    X, _ = gp_inputs.gp_problem(n, seed=31, k=1)
+    A = oracle.gp_assemble(X, 1.0, 1.0, 0.1)
+    L, _ = oracle.cholesky(A)
+    L1 = L.copy()
+    L1[40, 7] += 1e-6  # a planted error
+    Z = np.random.default_rng(3).standard_normal((n, 3))
+    E = A - L1 @ L1.T
+    est, num, den = oracle.backward_error_estimate(L1, Z, A=A)
+    np.testing.assert_allclose(num, np.sum((E @ Z) ** 2), rtol=1e-9)
+    np.testing.assert_allclose(den, np.sum((A @ Z) ** 2), rtol=1e-12)
+    # the matrix-free GP path sees the same matrix
+    est2, num2, den2 = oracle.backward_error_estimate(L1, Z, Xfeat=X, lengthscale=1.0, variance=1.0, noise=0.1)
+    np.testing.assert_allclose([num2, den2], [num, den], rtol=1e-12)
+
+
+def test_backward_error_estimate_is_unbiased():
+    # with many Gaussian probes the estimate approaches the exact checker
+    n = 120
+    X, _ = gp_inputs.gp_problem(n, seed=32, k=1)
+    A = oracle.gp_assemble(X, 1.0, 1.0, 0.1)
+    L, _ = oracle.cholesky(A)
+    L[70:, 3] += 1e-7
+    exact = oracle.backward_error(A, L)
+    Z = np.random.default_rng(4).standard_normal((n, 400))
+    est, _, _ = oracle.backward_error_estimate(L, Z, A=A)
+    ratio = est / exact
+    # ||A Z||^2 / k estimates ||A||_F^2 as well; both are chi-square-like
+    assert 0.8 <= ratio <= 1.25, ratio
