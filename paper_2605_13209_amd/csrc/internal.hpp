@@ -68,8 +68,8 @@ void launch_update(void *tiles, int store, int b, int64_t N, int64_t p0, int pw,
                    hipStream_t s, int64_t max_wg = 0, const void *p16 = nullptr);
 // FP16 copy of the finished panel columns [c0, c0 + pw) for tile rows
 // [c0, N), in the update kernel's layout: p16 holds N * 16 chunks of
-// 128 x 64 halves (panel width <= 8).
-constexpr int64_t kP16BytesPerTileRow = 16 * 128 * 64 * 2;
+// 128 x 64 halves (panel width <= 16).
+constexpr int64_t kP16BytesPerTileRow = 32 * 128 * 64 * 2;
 void launch_panel_f16(const void *tiles, int64_t N, int64_t c0, int pw, void *p16,
                       const int64_t *info, hipStream_t s);
 

@@ -333,7 +333,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void u
 // FP32 kernel, wave-local row 4q + s2) hit 8 different 16-byte bank groups
 // per 8 lanes.  Converting once per panel instead of once per use also
 // removes the transpose from the update's inner loop.
-constexpr int P16_CHMAX = 16;  // chunks of 64 columns per tile row (panel width <= 8)
+constexpr int P16_CHMAX = 32;  // chunks of 64 columns per tile row (panel width <= 16)
 constexpr int P16_CHUNK = BT * 64;  // halves per chunk
 
 __global__ __launch_bounds__(256) void panel_f16_kernel(const float *__restrict__ tiles, int64_t N,

@@ -39,9 +39,9 @@ def test_factor_bytes():
     assert P.chol_factor_bytes(1024, "fp64", 128) == 256 + (36 + 8) * 128 * 128 * 8
     assert P.chol_factor_bytes(1000, "fp32", 128) == 256 + (36 + 8) * 128 * 128 * 4
     assert P.chol_factor_bytes(65536, "fp64", 128) == 256 + (512 * 513 // 2 + 512) * 128 * 128 * 8
-    # FP16 form: FP32 tiles plus two FP16 panel buffers of N * 16 chunks of 128 x 64 halves
+    # FP16 form: FP32 tiles plus two FP16 panel buffers of N * 32 chunks of 128 x 64 halves
     assert P.chol_factor_bytes(1024, "fp16_scaled", 128) == \
-        256 + (36 + 8) * 128 * 128 * 4 + 2 * 8 * 16 * 128 * 64 * 2
+        256 + (36 + 8) * 128 * 128 * 4 + 2 * 8 * 32 * 128 * 64 * 2
     assert P.chol_factor_bytes(0, "fp64", 64) == 256
     assert P.chol_factor_bytes(10, "fp64", 96) == 0
     assert P.chol_factor_bytes(-1, "fp64", 64) == 0
@@ -54,7 +54,7 @@ def test_options_roundtrip_and_validation():
     assert P.get_option("panel_width") == 4
     P.set_option("panel_width", old)
     with pytest.raises(P.CholError):
-        P.set_option("panel_width", 9)
+        P.set_option("panel_width", 17)
     with pytest.raises(P.CholError):
         P.set_option("no_such_knob", 1)
     assert P.get_option("no_such_knob") == -1

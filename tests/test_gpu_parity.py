@@ -166,7 +166,7 @@ def test_schedule_invariance_bitwise():
     A = dev(oracle.gp_assemble(X, 1.0, 1.0, 0.1))
     outs = []
     try:
-        for w, la in [(1, 0), (2, 1), (4, 1), (3, 0), (8, 1), (6, 0)]:
+        for w, la in [(1, 0), (2, 1), (4, 1), (3, 0), (8, 1), (6, 0), (16, 1)]:
             P.set_option("panel_width", w)
             P.set_option("lookahead", la)
             for prec in ("fp64", "fp32"):
@@ -382,11 +382,11 @@ def test_fp16_scaled_factor_and_refine():
             assert err <= 1e-10, (method, c, err)
 
 
-@pytest.mark.parametrize("pw", [2, 3])
-def test_fp16_scaled_lookahead_invariance(pw):
+@pytest.mark.parametrize("pw,n", [(2, 1300), (3, 1300), (16, 2250)])
+def test_fp16_scaled_lookahead_invariance(pw, n):
     # the two FP16 panel buffers alternate between panels; with and without
-    # lookahead (ragged n, a partial last panel) the factors are identical
-    n = 1300
+    # lookahead (ragged n, a partial last panel) the factors are identical;
+    # width 16 (the FP16 form's widest: 32 chunks of 64 columns per tile row)
     X, _ = gp_inputs.gp_problem(n, seed=4)
     Ad = P.gp_assemble(torch.from_numpy(X).cuda(), 0.5, 1.0, 1.0)
     Ls = []
