@@ -101,7 +101,9 @@ __global__ __launch_bounds__(256) void symm_residual_kernel(
     if (Jb + 1 < nb) fetch(Jb + 1);
     const double *ab = at[buf];
     const double *xb = xs[buf];
-#pragma unroll
+    // not unrolled: unrolling hoists every LDS read of the block into
+    // registers (500 per lane, one wave per SIMD)
+#pragma unroll 1
     for (int j2 = 0; j2 < 16; j2 += NA) {
 #pragma unroll
       for (int u = 0; u < NA; ++u) {
