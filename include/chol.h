@@ -270,6 +270,11 @@ void chol_profile_reset(void);
  *                  (see chol_profile_read).
  * "solve_spin_max": polls allowed per wait inside chol_solve (default 2^20,
  *                  about a second; rows of a solve that runs out become NaN).
+ * "first_panel_width": tile columns of the first panel (1..16; 0 = the
+ *                  panel width; default 0).  With lookahead the first
+ *                  panel's tile columns are packed first and factored while
+ *                  the rest of A is packed; a narrower first panel lets the
+ *                  first trailing update start sooner.
  * "bulk_wg_cap"  : with lookahead, the far trailing update runs with at most
  *                  this many (persistent) workgroups, leaving slots for the
  *                  next panel's kernels (default 0 = no cap: one workgroup

@@ -40,6 +40,7 @@ struct Options {
   std::atomic<int64_t> graph{0};
   std::atomic<int64_t> profile{0};
   std::atomic<int64_t> bulk_wg_cap{0};  // workgroups of the bulk update under lookahead (0 = all)
+  std::atomic<int64_t> first_panel_width{0};  // tile columns of the first panel (0 = the panel width)
   std::atomic<int64_t> solve_spin_max{1 << 20};  // bound of each wait inside a solve
 };
 Options g_opt;
@@ -256,6 +257,9 @@ int chol_set_option(const char *key, int64_t value) {
   } else if (!strcmp(key, "bulk_wg_cap")) {
     if (value < 0 || value > (int64_t)1 << 30) return -2;
     g_opt.bulk_wg_cap = value;
+  } else if (!strcmp(key, "first_panel_width")) {
+    if (value < 0 || value > 16) return -2;
+    g_opt.first_panel_width = value;
   } else {
     return -1;
   }
@@ -270,6 +274,7 @@ int64_t chol_get_option(const char *key) {
   if (!strcmp(key, "graph")) return g_opt.graph;
   if (!strcmp(key, "profile")) return g_opt.profile;
   if (!strcmp(key, "bulk_wg_cap")) return g_opt.bulk_wg_cap;
+  if (!strcmp(key, "first_panel_width")) return g_opt.first_panel_width;
   if (!strcmp(key, "solve_spin_max")) return g_opt.solve_spin_max;
   return -1;
 }
@@ -338,17 +343,17 @@ int gp_assemble(const double *X, int64_t n, int64_t d, int64_t ldx, double lengt
   return hipGetLastError() == hipSuccess ? CHOL_OK : CHOL_ERR_HIP;
 }
 
-// FP16 panel buffer of the panel starting at column c0 (panels of width w
-// alternate between the two buffers).
-static void *panel_buf(const chol_factor_s *F, int64_t c0, int64_t w) {
+// FP16 panel buffer of panel number p (consecutive panels alternate
+// between the two buffers).
+static void *panel_buf(const chol_factor_s *F, size_t p) {
   if (!F->p16) return nullptr;
-  return (char *)F->p16 + (size_t)((c0 / w) & 1) * (size_t)F->N * (size_t)kP16BytesPerTileRow;
+  return (char *)F->p16 + (p & 1) * (size_t)F->N * (size_t)kP16BytesPerTileRow;
 }
 
 // Steps 1-2 (and the in-panel Step 3, in the storage precision) of panel
-// columns [c0, c1); in the FP16 form the finished panel is then converted
-// for the updates that use it.
-static void factor_panel(chol_factor_s *F, int64_t c0, int64_t c1, int64_t w, int st,
+// number p, columns [c0, c1); in the FP16 form the finished panel is then
+// converted for the updates that use it.
+static void factor_panel(chol_factor_s *F, size_t p, int64_t c0, int64_t c1, int st,
                          hipStream_t s) {
   const int64_t N = F->N;
   const int b = F->b;
@@ -358,55 +363,66 @@ static void factor_panel(chol_factor_s *F, int64_t c0, int64_t c1, int64_t w, in
     if (c + 1 < c1)
       update(F->tiles, st, b, N, c, 1, c + 1, c1, /*band*/ 1, 8, /*fp16*/ 0, F->d_info, s);
   }
-  if (F->p16) launch_panel_f16(F->tiles, N, c0, (int)(c1 - c0), panel_buf(F, c0, w), F->d_info, s);
+  if (F->p16) launch_panel_f16(F->tiles, N, c0, (int)(c1 - c0), panel_buf(F, p), F->d_info, s);
 }
 
 // Enqueue the whole factorisation (clear info, pack, column steps) on the
 // factor's stream and, with lookahead, the side stream joined back into it.
+// Panels: the first w0 tile columns, then w at a time.
 static int enqueue_factor(chol_factor_s *F, SideCtx *ctx, const double *A, int64_t lda, int st,
-                          double pack_scale, int64_t w, int S, bool la) {
+                          double pack_scale, int64_t w, int64_t w0, int S, bool la) {
   const int64_t N = F->N, n = F->n;
   const int b = F->b;
   const int fp16 = F->precision == CHOL_FP16_SCALED;
   hipStream_t s = F->stream;
+  std::vector<int64_t> pb{0};  // panel p covers [pb[p], pb[p + 1])
+  for (int64_t c = std::min<int64_t>(w0, N); ; c = std::min<int64_t>(c + w, N)) {
+    pb.push_back(c);
+    if (c >= N) break;
+  }
+  const size_t P = pb.size() - 1;
   launch_clear_i64(F->d_info, 1, s);
-  launch_pack(A, n, lda, F->tiles, st, b, N, pack_scale, s);
   if (!la) {
-    for (int64_t c0 = 0; c0 < N; c0 += w) {
-      const int64_t c1 = std::min<int64_t>(c0 + w, N);
-      factor_panel(F, c0, c1, w, st, s);
+    launch_pack(A, n, lda, F->tiles, st, b, N, pack_scale, s);
+    for (size_t p = 0; p < P; ++p) {
+      const int64_t c0 = pb[p], c1 = pb[p + 1];
+      factor_panel(F, p, c0, c1, st, s);
       if (c1 < N)
         update(F->tiles, st, b, N, c0, (int)(c1 - c0), c1, N, /*tri*/ 0, S, fp16, F->d_info, s, 0,
-               panel_buf(F, c0, w));
+               panel_buf(F, p));
     }
   } else {
-    hipStream_t p = ctx->side;
+    // the first panel's tile columns are packed first and factored on the
+    // side stream while the main stream packs the rest
+    hipStream_t q = ctx->side;
+    launch_pack(A, n, lda, F->tiles, st, b, N, pack_scale, s, 0, pb[1]);
     HIP_OK(hipEventRecord(ctx->ev_fork, s));
-    HIP_OK(hipStreamWaitEvent(p, ctx->ev_fork, 0));
-    factor_panel(F, 0, std::min<int64_t>(w, N), w, st, p);
-    for (int64_t c0 = 0; c0 < N; c0 += w) {
-      const int64_t c1 = std::min<int64_t>(c0 + w, N);  // current panel [c0, c1)
-      const int64_t n1 = std::min<int64_t>(c1 + w, N);  // next panel [c1, n1)
-      HIP_OK(hipEventRecord(ctx->ev_panel, p));          // panel [c0, c1) finished
+    HIP_OK(hipStreamWaitEvent(q, ctx->ev_fork, 0));
+    factor_panel(F, 0, 0, pb[1], st, q);
+    launch_pack(A, n, lda, F->tiles, st, b, N, pack_scale, s, pb[1], N);
+    HIP_OK(hipEventRecord(ctx->ev_bulk, s));  // everything packed
+    for (size_t p = 0; p < P; ++p) {
+      const int64_t c0 = pb[p], c1 = pb[p + 1];   // current panel [c0, c1)
+      const int64_t n1 = p + 2 <= P ? pb[p + 2] : N;  // next panel [c1, n1)
+      HIP_OK(hipEventRecord(ctx->ev_panel, q));      // panel p finished
       if (c1 < N) {
         // next panel: its update by this panel (after the previous bulk update,
-        // which also wrote it), then its Steps 1-2, all on the side stream.
-        if (c0 > 0) HIP_OK(hipStreamWaitEvent(p, ctx->ev_bulk, 0));
-        update(F->tiles, st, b, N, c0, (int)(c1 - c0), c1, n1, /*band*/ 1, 8, fp16, F->d_info, p, 0,
-               panel_buf(F, c0, w));
-        factor_panel(F, c1, n1, w, st, p);
+        // which also wrote it, or after the packing), then its Steps 1-2, all
+        // on the side stream.
+        HIP_OK(hipStreamWaitEvent(q, ctx->ev_bulk, 0));
+        update(F->tiles, st, b, N, c0, (int)(c1 - c0), c1, n1, /*band*/ 1, 8, fp16, F->d_info, q, 0,
+               panel_buf(F, p));
+        factor_panel(F, p + 1, c1, n1, st, q);
       }
-      // bulk update of the columns right of the next panel, on the main
-      // stream; while a next panel exists its workgroups are capped so that
-      // the side stream's kernels find free slots.
+      // bulk update of the columns right of the next panel, on the main stream
       HIP_OK(hipStreamWaitEvent(s, ctx->ev_panel, 0));
       if (n1 < N) {
         update(F->tiles, st, b, N, c0, (int)(c1 - c0), n1, N, /*tri*/ 0, S, fp16, F->d_info, s,
-               g_opt.bulk_wg_cap.load(), panel_buf(F, c0, w));
+               g_opt.bulk_wg_cap.load(), panel_buf(F, p));
       }
       HIP_OK(hipEventRecord(ctx->ev_bulk, s));
     }
-    HIP_OK(hipEventRecord(ctx->ev_join, p));
+    HIP_OK(hipEventRecord(ctx->ev_join, q));
     HIP_OK(hipStreamWaitEvent(s, ctx->ev_join, 0));
   }
   // inverted diagonal blocks for the solves
@@ -488,12 +504,14 @@ int chol_factor_ex(const double *A, int64_t n, int64_t lda, int precision,
   const int64_t la_opt =
       (opts && opts->lookahead >= 0) ? (int64_t)opts->lookahead : g_opt.lookahead.load();
   const bool la = la_opt != 0 && N > w;
+  const int64_t fw = g_opt.first_panel_width.load();
+  const int64_t w0 = fw > 0 ? std::min<int64_t>(fw, w) : w;
 
 
   // Stream capture is not allowed on the legacy NULL stream: direct launches there.
   const bool graph = (opts && opts->graph >= 0 ? opts->graph != 0 : g_opt.graph != 0) &&
                      precision != CHOL_FP16_SCALED && !g_opt.profile && s != nullptr;
-  GraphKey gk{A, n, lda, precision, tile, w, la ? 1 : 0, S, workspace};
+  GraphKey gk{A, n, lda, precision, tile, w * 32 + w0, la ? 1 : 0, S, workspace};
   if (graph) {
     int dev = 0;
     (void)hipGetDevice(&dev);
@@ -517,7 +535,7 @@ int chol_factor_ex(const double *A, int64_t n, int64_t lda, int precision,
       return CHOL_ERR_HIP;
     }
   }
-  rc = enqueue_factor(F, ctx, A, lda, st, pack_scale, w, S, la);
+  rc = enqueue_factor(F, ctx, A, lda, st, pack_scale, w, w0, S, la);
   if (rc != CHOL_OK) {
     if (graph) {
       hipGraph_t g = nullptr;

@@ -43,9 +43,11 @@ void launch_clear_i64(int64_t *p, int count, hipStream_t s);
 // *out = max_i A(i, i) (column-major, leading dimension lda).
 void launch_max_diag(const double *A, int64_t lda, int64_t n, double *out, hipStream_t s);
 
-// Column-major FP64 A (lower) -> packed tiles, scaled by `scale`, identity padding.
+// Column-major FP64 A (lower) -> packed tiles, scaled by `scale`, identity
+// padding; only tile columns [c_begin, c_end) (c_end < 0: to the last).
 void launch_pack(const double *A, int64_t n, int64_t lda, void *tiles, int store, int b,
-                 int64_t N, double scale, hipStream_t s);
+                 int64_t N, double scale, hipStream_t s, int64_t c_begin = 0,
+                 int64_t c_end = -1);
 // Packed tiles -> dense column-major FP64 L (upper set to zero), times `scale`.
 void launch_unpack(const void *tiles, int store, int b, int64_t N, int64_t n, double scale,
                    double *L, int64_t ldl, hipStream_t s);

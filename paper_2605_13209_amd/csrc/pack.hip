@@ -11,8 +11,8 @@ namespace {
 template <typename T>
 __global__ __launch_bounds__(256) void pack_kernel(const double *__restrict__ A, int64_t n,
                                                    int64_t lda, T *__restrict__ tiles, int b,
-                                                   int64_t N, double scale) {
-  const int64_t i = blockIdx.x, c = blockIdx.y;
+                                                   int64_t N, double scale, int64_t c_begin) {
+  const int64_t i = blockIdx.x, c = c_begin + blockIdx.y;
   if (i < c) return;
   T *dst = tiles + tile_index(i, c, N) * (int64_t)b * b;
   const int bb = b * b, lgb = 31 - __clz(b);  // b is a power of two
@@ -50,15 +50,16 @@ __global__ __launch_bounds__(256) void unpack_kernel(const T *__restrict__ tiles
 }  // namespace
 
 void launch_pack(const double *A, int64_t n, int64_t lda, void *tiles, int store, int b,
-                 int64_t N, double scale, hipStream_t s) {
-  if (N <= 0) return;
-  dim3 grid((unsigned)N, (unsigned)N);
+                 int64_t N, double scale, hipStream_t s, int64_t c_begin, int64_t c_end) {
+  if (c_end < 0 || c_end > N) c_end = N;
+  if (N <= 0 || c_begin < 0 || c_begin >= c_end) return;
+  dim3 grid((unsigned)N, (unsigned)(c_end - c_begin));
   if (store == STORE_F64)
     hipLaunchKernelGGL(pack_kernel<double>, grid, dim3(256), 0, s, A, n, lda, (double *)tiles, b,
-                       N, scale);
+                       N, scale, c_begin);
   else
     hipLaunchKernelGGL(pack_kernel<float>, grid, dim3(256), 0, s, A, n, lda, (float *)tiles, b, N,
-                       scale);
+                       scale, c_begin);
 }
 
 void launch_unpack(const void *tiles, int store, int b, int64_t N, int64_t n, double scale,

@@ -166,15 +166,18 @@ def test_schedule_invariance_bitwise():
     A = dev(oracle.gp_assemble(X, 1.0, 1.0, 0.1))
     outs = []
     try:
-        for w, la in [(1, 0), (2, 1), (4, 1), (3, 0), (8, 1), (6, 0), (16, 1)]:
+        for w, la, fw in [(1, 0, 0), (2, 1, 0), (4, 1, 0), (3, 0, 0), (8, 1, 0), (6, 0, 0), (16, 1, 0),
+                          (8, 1, 2), (4, 1, 1), (8, 0, 3)]:
             P.set_option("panel_width", w)
             P.set_option("lookahead", la)
+            P.set_option("first_panel_width", fw)
             for prec in ("fp64", "fp32"):
                 F = P.chol_factor(A, prec, 128)
                 outs.append((prec, host(P.chol_factor_to_dense(F))))
     finally:
         P.set_option("panel_width", 0)
         P.set_option("lookahead", 1)
+        P.set_option("first_panel_width", 0)
     for prec in ("fp64", "fp32"):
         ref = [L for p, L in outs if p == prec]
         for L in ref[1:]:
