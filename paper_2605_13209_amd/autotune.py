@@ -20,7 +20,7 @@ import numpy as np
 
 SIZES = (256, 512, 1024, 2048, 4096, 8192, 16384)
 TILES = (64, 128)
-WIDTHS = (1, 2, 4)
+WIDTHS = (1, 2, 4, 8)
 
 
 def _problem(n: int, seed: int = 0):
