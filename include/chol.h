@@ -253,7 +253,7 @@ void chol_profile_reset(void);
 /* ---- tuning knobs (process-wide; set before factorising) ---------------
  * "panel_width"  : tiles per outer step whose Step-3 update is applied in
  *                  one pass (1..16; 0 = automatic: 8 from 192 tile rows,
- *                  4 from 64, else 2, and 16 for CHOL_FP16_SCALED from 512
+ *                  4 from 64, else 8, and 16 for CHOL_FP16_SCALED from 512
  *                  tile rows; default 0).  Widths above 8 apply to
  *                  CHOL_FP16_SCALED only (FP64 and FP32 use 8 then).
  * "lookahead"    : 1 overlaps the next panel's Steps 1-2 with the current

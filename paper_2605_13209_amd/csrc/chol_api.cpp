@@ -495,7 +495,9 @@ int chol_factor_ex(const double *A, int64_t n, int64_t lda, int precision,
       (opts && opts->panel_width > 0) ? (int64_t)opts->panel_width : g_opt.panel_width.load();
   // (widths above 8 only for the FP16 form, whose update is bound by the
   // traffic of C rather than by the matrix cores)
-  int64_t w = pw_opt > 0 ? pw_opt : (N >= 192 ? 8 : (N >= 64 ? 4 : 2));
+  // automatic width, from the autotuner's sweep on MI355X: 8 for small
+  // (chain-bound) and large matrices, 4 in between
+  int64_t w = pw_opt > 0 ? pw_opt : (N >= 192 ? 8 : (N >= 64 ? 4 : 8));
   if (pw_opt <= 0 && precision == CHOL_FP16_SCALED && N >= 512) w = 16;  // 10 % faster at n = 131072
   if (precision != CHOL_FP16_SCALED && w > 8) w = 8;
   const int S =
