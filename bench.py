@@ -157,6 +157,7 @@ def main():
     B1_src = B16_src[:, :1]
     A = P.colmajor_empty(n, n)
     extra = {}
+    prof_mode = 2
 
     if wl.startswith("fp64"):
         ws = torch.empty(P.chol_factor_bytes(n, "fp64", tile), dtype=torch.uint8, device="cuda")
@@ -187,7 +188,9 @@ def main():
             raise RuntimeError(f"factorisation failed, info={F.info()}")
         P.chol_profile_reset()
         if not args.no_profile:
-            P.set_option("profile", 2)
+            # small orders are one panel (no whole-triangle launches): time every update launch
+            prof_mode = 1 if n < 192 * tile else 2
+            P.set_option("profile", prof_mode)
         t_step, t_asm, t_fac, t_s1, t_s16 = [], [], [], [], []
         torch.cuda.synchronize()
         wall0 = time.perf_counter()
@@ -281,8 +284,9 @@ def main():
                     "traffic_unit": "bytes per launch between L2 and the memory fabric (calibrated counters)",
                     "algorithmic_bytes_per_launch": TRAFFIC["algorithmic_bytes_per_launch"]
                     if measured_traffic(n, dtype) else None,
-                    "kernel": ("update_f64_kernel<0>" if dtype == "f64" else "update_f32_kernel<0>")
-                    + " (Step-3 update of the trailing triangle)", "launches": kl,
+                    "kernel": ("update_f64_kernel" if dtype == "f64" else "update_f32_kernel")
+                    + ("<0> (Step-3 update of the trailing triangle)" if prof_mode == 2
+                       else " (every Step-3 update launch)"), "launches": kl,
                     "avg_launch_us": round(kms * 1e3 / kl, 2),
                     "avg_launch_gflop": round(kfl / kl / 1e9, 4)}
 
