@@ -27,7 +27,7 @@ __device__ inline double readlane_f64(double v, int l) {
 // scaled and then subtracted from the later x_i (the same operations in the
 // same order as the row-wise substitution), column j + 1 of L being read
 // while column j is applied.
-// LEAN reads each reciprocal diagonal entry when it is used instead of all
+// LEAN reads each reciprocal diagonal entry one column ahead instead of all
 // of them up front (fewer registers live at once).
 template <int NB, int PP, bool LEAN = false>
 __device__ __forceinline__ void row_solve(double (&x)[NB], const double *l, const double *rdv) {
@@ -35,6 +35,8 @@ __device__ __forceinline__ void row_solve(double (&x)[NB], const double *l, cons
   if (!LEAN) {
 #pragma unroll
     for (int j = 0; j < NB; ++j) rv[j] = rdv[j];
+  } else {
+    rv[0] = rdv[0];  // then each entry one column ahead, with the column of L
   }
 #pragma unroll
   for (int i = 1; i < NB; ++i) col[0][i] = l[i * PP];
@@ -43,8 +45,9 @@ __device__ __forceinline__ void row_solve(double (&x)[NB], const double *l, cons
     if (j + 1 < NB) {
 #pragma unroll
       for (int i = j + 2; i < NB; ++i) col[(j + 1) & 1][i] = l[i * PP + j + 1];
+      if (LEAN) rv[j + 1] = rdv[j + 1];
     }
-    x[j] *= LEAN ? rdv[j] : rv[j];
+    x[j] *= rv[j];
 #pragma unroll
     for (int i = j + 1; i < NB; ++i) x[i] -= x[j] * col[j & 1][i];
     __builtin_amdgcn_sched_barrier(0);
