@@ -418,6 +418,7 @@ void trsm_dispatch(void *tiles, int store, int64_t N, int64_t c, const int64_t *
 
 void launch_potrf(void *tiles, int store, int b, int64_t N, int64_t c, int64_t *info,
                   hipStream_t s) {
+  if (c < 0 || c >= N) return;  // no such diagonal tile
   if (b == 128)
     potrf_dispatch<128>(tiles, store, N, c, info, s);
   else
