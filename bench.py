@@ -88,7 +88,7 @@ def cpu_baseline(n: int):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="fp64_n32768",
                     choices=["fp64_n32768", "fp64_n1024", "fp64_n65536", "mixed_n65536",
@@ -148,7 +148,7 @@ def main():
     n = args.n or {"fp64_n32768": 32768, "fp64_n1024": 1024, "fp64_n65536": 65536, "mixed_n65536": 65536}[wl]
     tile = args.tile
     steps, warmup = args.steps, args.warmup
-    if wl == "fp64_n1024" and steps == 5:
+    if wl == "fp64_n1024" and steps == 10:
         steps, warmup = 100, 5
 
     X_np, B_np = gp_inputs.gp_problem(n, d=8, k=16, seed=0)
@@ -339,7 +339,7 @@ def bench_cg(args):
     ws = torch.empty(P.cg_workspace_bytes(n, 1, 128), dtype=torch.uint8, device="cuda")
     Xs = P.colmajor_empty(n, 1)
     steps, warmup = args.steps, args.warmup
-    if steps == 5:
+    if steps == 10:
         steps = 3
     t_cg, its, rrs = [], [], []
     for rep in range(warmup + steps):
