@@ -275,6 +275,9 @@ void chol_profile_reset(void);
  *                  panel's tile columns are packed first and factored while
  *                  the rest of A is packed; a narrower first panel lets the
  *                  first trailing update start sooner.
+ * "f16_wide"     : 1 (default) runs the FP16 form's whole-triangle updates
+ *                  with 2 x 2 tiles per workgroup (half the operand traffic
+ *                  per flop), 0 with one tile per workgroup; same result.
  * "bulk_wg_cap"  : with lookahead, the far trailing update runs with at most
  *                  this many (persistent) workgroups, leaving slots for the
  *                  next panel's kernels (default 0 = no cap: one workgroup

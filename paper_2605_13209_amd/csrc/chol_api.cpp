@@ -41,6 +41,7 @@ struct Options {
   std::atomic<int64_t> profile{0};
   std::atomic<int64_t> bulk_wg_cap{0};  // workgroups of the bulk update under lookahead (0 = all)
   std::atomic<int64_t> first_panel_width{0};  // tile columns of the first panel (0 = the panel width)
+  std::atomic<int64_t> f16_wide{1};  // FP16 whole-triangle update with 2 x 2 tiles per workgroup
   std::atomic<int64_t> solve_spin_max{1 << 20};  // bound of each wait inside a solve
 };
 Options g_opt;
@@ -260,6 +261,10 @@ int chol_set_option(const char *key, int64_t value) {
   } else if (!strcmp(key, "first_panel_width")) {
     if (value < 0 || value > 16) return -2;
     g_opt.first_panel_width = value;
+  } else if (!strcmp(key, "f16_wide")) {
+    if (value < 0 || value > 1) return -2;
+    g_opt.f16_wide = value;
+    set_f16_wide((int)value);
   } else {
     return -1;
   }
@@ -275,6 +280,7 @@ int64_t chol_get_option(const char *key) {
   if (!strcmp(key, "profile")) return g_opt.profile;
   if (!strcmp(key, "bulk_wg_cap")) return g_opt.bulk_wg_cap;
   if (!strcmp(key, "first_panel_width")) return g_opt.first_panel_width;
+  if (!strcmp(key, "f16_wide")) return g_opt.f16_wide;
   if (!strcmp(key, "solve_spin_max")) return g_opt.solve_spin_max;
   return -1;
 }

@@ -68,6 +68,9 @@ void launch_trsm(void *tiles, int store, int b, int64_t N, int64_t c, const int6
 void launch_update(void *tiles, int store, int b, int64_t N, int64_t p0, int pw, int64_t k0,
                    int64_t k1, int mode, int super_tile, int fp16, const int64_t *info,
                    hipStream_t s, int64_t max_wg = 0, const void *p16 = nullptr);
+// Kernel choice for the FP16 form's whole-triangle updates (1: 2 x 2 tiles
+// per workgroup, the default; 0: one tile per workgroup).  Same result.
+void set_f16_wide(int on);
 // FP16 copy of the finished panel columns [c0, c0 + pw) for tile rows
 // [c0, N), in the update kernel's layout: p16 holds N * 16 chunks of
 // 128 x 64 halves (panel width <= 16).

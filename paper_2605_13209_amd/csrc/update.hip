@@ -472,6 +472,135 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void u
   }  // tiles of this workgroup
 }
 
+// The same update over the whole trailing triangle with 2 x 2 tiles per
+// workgroup (256 x 256 outputs, 8 waves of 128 x 64): every panel chunk
+// staged in LDS serves twice the flops of the one-tile kernel, halving the
+// L2 -> LDS operand traffic per flop, which bounds the FP16 form once the
+// pass is wide.  Super-tile (I, K) covers tile rows 2I, 2I+1 and tile
+// columns 2K, 2K+1 of the region; quadrants above the diagonal or past the
+// matrix are computed on whatever the LDS holds and never loaded or stored.
+// LDS per stage: the two A row chunks and the two B row chunks (64 KB).
+__global__ __launch_bounds__(512) void update_f16_wide_kernel(
+    float *__restrict__ tiles, const _Float16 *__restrict__ p16, int64_t N, int pw, int64_t k0,
+    int S, int64_t G, int64_t G8, const int64_t *__restrict__ info) {
+  constexpr int NKS = 2;  // k-steps of 32 per chunk
+  if (*info != 0) return;
+  __shared__ __attribute__((aligned(16))) _Float16 lds[2][4][P16_CHUNK];  // A0 A1 B0 B1
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int g = lane >> 4, q = lane & 15;
+  const int wm = wave >> 2, wn = wave & 3;  // tile row 2I + wm; tile column 2K + wn/2
+  const int wu = __builtin_amdgcn_readfirstlane(wave);
+  const int64_t R2 = (N - k0 + 1) / 2;
+  const int64_t per = gridDim.x / 8;
+  for (int64_t pos = blockIdx.x / 8; pos < G8; pos += per) {
+    const int64_t t = (blockIdx.x % 8) * G8 + pos;
+    if (t >= G) break;
+    int64_t IR, KR;
+    map_triangle(t, R2, S, IR, KR);
+    const int64_t ib = k0 + 2 * IR, kb = k0 + 2 * KR;  // first tile row / column
+    const int64_t i = ib + wm, k = kb + (wn >> 1);
+    const bool valid = i < N && k <= i;  // wave-uniform
+    const int cb = 64 * (wn & 1);        // the wave's first column in tile (i, k)
+    float *C = valid ? tiles + tile_index(i, k, N) * (int64_t)(BT * BT) : nullptr;
+    const int nstage = 2 * pw;
+    // chunk s: wave w moves 8 KB of operand chunk w / 2 (A0, A1, B0, B1)
+    const int op = wu >> 1;
+    const int64_t orow = (op < 2 ? ib : kb) + (op & 1);  // tile row of that operand chunk
+    auto dma = [&](int s) {
+      if (orow >= N) return;  // rows past the matrix: nothing to stage
+      const _Float16 *src = p16 + (orow * P16_CHMAX + s) * (int64_t)P16_CHUNK;
+#pragma unroll
+      for (int c = 0; c < 8; ++c) {
+        const int off = ((wu & 1) * 8 + c) * 512;  // halves (1 KB)
+        lds_dma16(src + off, lane * 16, &lds[s & 1][op][off]);
+      }
+    };
+    v4f acc[2][4][4];  // [row half][s2][u]
+    if (valid) {
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const float *col = C + (cb + 4 * q + u) * BT + 64 * h + 16 * g;
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            float v[4];
+            *(uint4 *)&v[0] = *(const uint4 *)(col + 4 * e);
+#pragma unroll
+            for (int s2 = 0; s2 < 4; ++s2) acc[h][s2][u][e] = -v[s2];
+          }
+        }
+    } else {
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int s2 = 0; s2 < 4; ++s2)
+#pragma unroll
+          for (int u = 0; u < 4; ++u) acc[h][s2][u] = v4f{0.f, 0.f, 0.f, 0.f};
+    }
+    dma(0);
+    if (nstage > 1) dma(1);
+    wait_vmem();
+    __syncthreads();
+    auto frag = [&](const _Float16 *l, int r0, int s2, int ks) -> v8h {
+      const int r = r0 + 4 * q + s2;
+      const int sg = (4 * ks + g) ^ ((r >> 2) & 7);
+      return *(const v8h *)(l + r * 64 + 8 * sg);
+    };
+    v8h fa[2][8], fb[2][4];
+#pragma unroll
+    for (int x = 0; x < 8; ++x) fa[0][x] = frag(lds[0][wm], 64 * (x >> 2), x & 3, 0);
+#pragma unroll
+    for (int x = 0; x < 4; ++x) fb[0][x] = frag(lds[0][2 + (wn >> 1)], cb, x, 0);
+    const int nk = nstage * NKS;
+    auto step = [&](int kt, int cur) {
+      const int s = kt / NKS, ks = kt % NKS;
+      const int nbuf = ((kt + 1) / NKS) & 1, nks = (kt + 1) % NKS;
+#pragma unroll
+      for (int x = 0; x < 8; ++x)  // next k-step (stale but in-bounds after the last)
+        fa[cur ^ 1][x] = frag(lds[nbuf][wm], 64 * (x >> 2), x & 3, nks);
+#pragma unroll
+      for (int x = 0; x < 4; ++x) fb[cur ^ 1][x] = frag(lds[nbuf][2 + (wn >> 1)], cb, x, nks);
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int s2 = 0; s2 < 4; ++s2)
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+            acc[h][s2][u] = __builtin_amdgcn_mfma_f32_16x16x32_f16(fa[cur][4 * h + s2], fb[cur][u],
+                                                                    acc[h][s2][u], 0, 0, 0);
+      __builtin_amdgcn_sched_group_barrier(0x100, 12, 0);
+      __builtin_amdgcn_sched_group_barrier(0x008, 32, 0);
+      __builtin_amdgcn_sched_barrier(0);
+      if (ks == NKS - 2) {
+        wait_vmem();
+        __syncthreads();
+        if (s + 2 < nstage) dma(s + 2);
+      }
+    };
+    for (int kt = 0; kt < nk; kt += 2) {
+      step(kt, 0);
+      step(kt + 1, 1);
+    }
+    if (valid) {
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          float *col = C + (cb + 4 * q + u) * BT + 64 * h + 16 * g;
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            float v[4];
+#pragma unroll
+            for (int s2 = 0; s2 < 4; ++s2) v[s2] = -acc[h][s2][u][e];
+            *(uint4 *)(col + 4 * e) = *(const uint4 *)&v[0];
+          }
+        }
+    }
+    __syncthreads();  // every wave's last LDS read before the next super-tile's DMA
+  }  // super-tiles of this workgroup
+}
+
 // Portable fallback for tile side 64 (small problems): one workgroup of 256
 // threads per 64 x 64 tile, plain FP64 FMAs, panel read through LDS.
 template <typename T>
@@ -521,6 +650,11 @@ __global__ __launch_bounds__(256) void update64_kernel(T *__restrict__ tiles, in
 
 }  // namespace
 
+// 1: the FP16 form's whole-triangle updates use the 2 x 2-tile kernel
+// (bitwise the same result as the one-tile kernel).
+static int g_f16_wide = 1;
+void set_f16_wide(int on) { g_f16_wide = on ? 1 : 0; }
+
 void launch_update(void *tiles, int store, int b, int64_t N, int64_t p0, int pw, int64_t k0,
                    int64_t k1, int mode, int super_tile, int fp16, const int64_t *info,
                    hipStream_t s, int64_t max_wg, const void *p16) {
@@ -541,7 +675,15 @@ void launch_update(void *tiles, int store, int b, int64_t N, int64_t p0, int pw,
     if (max_wg >= 8 && nwg > max_wg) nwg = (max_wg / 8) * 8;  // persistent: fewer workgroups
     const dim3 grid((unsigned)nwg);
     if (fp16 && !p16) return;  // the FP16 form needs its converted panel
-    if (fp16 && mode == 0)
+    if (fp16 && mode == 0 && R >= 16 && g_f16_wide) {
+      // 2 x 2 tiles per workgroup over the super-tile triangle
+      const int64_t R2 = (R + 1) / 2, G2 = triangle_count(R2), G28 = (G2 + 7) / 8;
+      int64_t nw = 8 * G28;
+      if (max_wg >= 8 && nw > max_wg) nw = (max_wg / 8) * 8;
+      const int S2 = super_tile > 1 ? super_tile / 2 : 1;
+      hipLaunchKernelGGL(update_f16_wide_kernel, dim3((unsigned)nw), dim3(512), 0, s,
+                         (float *)tiles, (const _Float16 *)p16, N, pw, k0, S2, G2, G28, info);
+    } else if (fp16 && mode == 0)
       hipLaunchKernelGGL(update_f16_kernel<0>, grid, dim3(256), 0, s, (float *)tiles,
                          (const _Float16 *)p16, N, pw, k0, K, super_tile, G, G8, info);
     else if (fp16)

@@ -402,6 +402,27 @@ def test_fp16_scaled_lookahead_invariance(pw, n):
     assert be <= 5e-3, be
 
 
+def test_fp16_wide_update_bitwise():
+    """The 2 x 2-tile FP16 trailing update (used from 16 trailing tile rows)
+    gives the same factor, bit for bit, as the one-tile kernel, with and
+    without lookahead (ragged n: a partial last super-tile row)."""
+    n = 4100
+    X, _ = gp_inputs.gp_problem(n, seed=6)
+    Ad = P.gp_assemble(torch.from_numpy(X).cuda(), 0.5, 1.0, 1.0)
+    Ls = []
+    try:
+        for wide, la in ((0, 1), (1, 1), (1, 0)):
+            P.set_option("f16_wide", wide)
+            F = P.chol_factor(Ad, "fp16_scaled", 128, panel_width=4, lookahead=la)
+            assert F.info() == 0
+            Ls.append(host(P.chol_factor_to_dense(F)))
+    finally:
+        P.set_option("f16_wide", 1)
+    assert np.array_equal(Ls[0], Ls[1]) and np.array_equal(Ls[1], Ls[2])
+    be = oracle.backward_error(oracle.gp_assemble(X, 0.5, 1.0, 1.0), Ls[1])
+    assert be <= 5e-3, be
+
+
 def test_fp16_scaled_solve_scaling():
     """chol_solve with the scaled factor returns A^-1 b (not H^-1 b)."""
     n = 600
