@@ -470,7 +470,7 @@ def bench_fp16(args):
         ach = kfl / (kms * 1e-3) / 1e12
         roofline = {"bound": "mfma", "achieved": round(ach, 3), "peak": FP16_PEAK_TFLOPS,
                     "unit": "TFLOP/s", "frac": round(ach / FP16_PEAK_TFLOPS, 4), "traffic": None,
-                    "kernel": "update_f16_kernel (Step-3 update of the trailing triangle)",
+                    "kernel": "update_f16_wide_kernel (Step-3 update of the trailing triangle, 2 x 2 tiles per workgroup)",
                     "launches": kl, "avg_launch_us": round(kms * 1e3 / kl, 2),
                     "avg_launch_gflop": round(kfl / kl / 1e9, 4)}
     print(json.dumps({"metric": METRIC, "value": round(flops / (ms * 1e-3) / 1e9, 2), "unit": "GFLOP/s",
