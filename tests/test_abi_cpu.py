@@ -105,3 +105,15 @@ def test_cg_workspace_bytes():
     assert P.cg_workspace_bytes(n, 17) == 0 and P.cg_workspace_bytes(n, 0) == 0
     assert P.cg_workspace_bytes(n, 1, 96) == 0
     assert P.cg_workspace_bytes(0, 1) == al(3 * 16 * 8 + 3 * 16 * 4)
+
+
+def test_schedule_options_roundtrip():
+    for key, good, bad in (("first_panel_width", 3, 17), ("f16_wide", 0, 2), ("panel_width", 16, 17),
+                           ("bulk_wg_cap", 64, -1), ("solve_spin_max", 100, 0)):
+        old = P.get_option(key)
+        P.set_option(key, good)
+        assert P.get_option(key) == good
+        with pytest.raises(P.CholError):
+            P.set_option(key, bad)
+        P.set_option(key, old)
+        assert P.get_option(key) == old
