@@ -1,6 +1,6 @@
 """GPU parity: the HIP path (through the C ABI) against the CPU oracle.
 
-Tolerances (derivations in DESIGN.md, "Parity bar"):
+Tolerances (each derived from the arithmetic of the step it checks):
 * integer / exact-arithmetic cases (known L0): bit-exact;
 * GP assembly: entries within 4 ulp (only exp differs; sums are unfused);
 * FP64 factor: backward error ||A - L L^T||_F / ||A||_F <= 1e-12, and the
