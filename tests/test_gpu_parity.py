@@ -336,6 +336,56 @@ def test_full_size_sampled_parity():
     assert oracle.certificate(r, x, hp[2]) <= 1e-10
 
 
+def test_full_size_mixed_fp32_n65536():
+    """The mixed-precision bench configuration (n = 65536, SE lengthscale 1,
+    noise 0.1, one right-hand side, FP32 factor, FP64 A for the residuals):
+    IR and factor-preconditioned CG both reach the 1e-10 certificate as
+    recomputed by the oracle from the features (matrix-free residual, long
+    double), and agree with each other within the sum of their bounds."""
+    torch.cuda.empty_cache()
+    n = 65536
+    hp = (1.0, 1.0, 0.1)
+    X, B = gp_inputs.gp_problem(n, seed=0, k=1)
+    Ad = P.gp_assemble(torch.from_numpy(X).cuda(), *hp, full=False)
+    F = P.chol_factor(Ad, "fp32", 128)
+    assert F.info() == 0
+    xs = {}
+    for method in ("ir", "pcg"):
+        r = P.chol_refine_solve(F, dev(B), A=Ad, noise=hp[2], tol=1e-10, method=method, max_iter=60)
+        assert r.converged and r.cert <= 1e-10, (method, r.iters, r.cert)
+        x = host(r.X)[:, 0]
+        res = oracle.gp_residual(X, *hp, x, B[:, 0])
+        assert oracle.certificate(res, x, hp[2]) <= 1e-10, method
+        xs[method] = x
+    gap = np.linalg.norm(xs["ir"] - xs["pcg"]) / np.linalg.norm(xs["ir"])
+    assert gap <= 2e-10, gap
+    del F, Ad
+    torch.cuda.empty_cache()
+
+
+def test_full_size_mixed_fp16_n131072():
+    """The FP16 bench configuration (n = 131072, SE lengthscale 0.5, noise 1,
+    eight right-hand sides; diagonally scaled FP16 update, FP32 storage, IR
+    against the FP64 A): every column certified to 1e-10 by the oracle's
+    matrix-free residual."""
+    torch.cuda.empty_cache()
+    n, k = 131072, 8
+    hp = (0.5, 1.0, 1.0)
+    X, B = gp_inputs.gp_problem(n, d=8, k=k, seed=0)
+    Ad = P.colmajor_empty(n, n)
+    P.gp_assemble(torch.from_numpy(X).cuda(), *hp, full=False, out=Ad)
+    F = P.chol_factor(Ad, "fp16_scaled", 128)
+    assert F.info() == 0
+    r = P.chol_refine_solve(F, dev(B), A=Ad, noise=hp[2], tol=1e-10, method="ir", max_iter=60)
+    assert r.converged and r.cert <= 1e-10, (r.iters, r.cert)
+    x = host(r.X)
+    del F, Ad, r
+    torch.cuda.empty_cache()
+    res = oracle.gp_residual(X, *hp, x, B)
+    for c in range(k):
+        assert oracle.certificate(res[:, c], x[:, c], hp[2]) <= 1e-10, c
+
+
 # ----------------------------------------------------------- edge cases ---
 
 def test_empty_and_tiny():
