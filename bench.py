@@ -102,7 +102,7 @@ def main():
     ap.add_argument("--lookahead", type=int, default=-1)
     ap.add_argument("--super-tile", type=int, default=0)
     ap.add_argument("--cpu-n", type=int, default=0,
-                    help="order of the CPU oracle sample (0: 12288 for Cholesky, 6144 for CG)")
+                    help="order of the CPU oracle sample (0: 12288 for Cholesky, 10240 for CG)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--cg-max-iter", type=int, default=0,
@@ -414,7 +414,7 @@ def bench_cg(args):
                         "relres_true": chol_rel},
            "speedup_cg_vs_cholesky": round(float(np.mean(t_ch)) / ms, 3) if t_ch else None}
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline_cg(args.cpu_n or 6144, eps)
+        out["cpu_baseline"] = cpu_baseline_cg(args.cpu_n or 10240, eps)
     print(json.dumps(out), flush=True)
 
 
