@@ -73,8 +73,13 @@ int cg_ctx(hipStream_t caller, CgCtx **out) {
     return CHOL_ERR_HIP;
   }
   if (hipEventCreateWithFlags(&c->ev[0], hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&c->ev[1], hipEventDisableTiming) != hipSuccess)
+      hipEventCreateWithFlags(&c->ev[1], hipEventDisableTiming) != hipSuccess) {
+    for (hipEvent_t e : c->ev)
+      if (e) (void)hipEventDestroy(e);
+    (void)hipHostFree(c->flags);
+    delete c;
     return CHOL_ERR_HIP;
+  }
   g_cg_ctx.push_back(c);
   *out = c;
   return CHOL_OK;

@@ -21,6 +21,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <initializer_list>
 #include <mutex>
 #include <vector>
 
@@ -83,9 +84,15 @@ int get_ctx(hipStream_t caller, SideCtx **out) {
   if (hipEventCreateWithFlags(&c->ev_fork, fl) != hipSuccess ||
       hipEventCreateWithFlags(&c->ev_panel, fl) != hipSuccess ||
       hipEventCreateWithFlags(&c->ev_bulk, fl) != hipSuccess ||
-      hipEventCreateWithFlags(&c->ev_join, fl) != hipSuccess)
+      hipEventCreateWithFlags(&c->ev_join, fl) != hipSuccess ||
+      hipMalloc((void **)&c->sync, kSyncWords * sizeof(int)) != hipSuccess) {
+    // a half-built context is released, so a later call can try again
+    for (hipEvent_t e : {c->ev_fork, c->ev_panel, c->ev_bulk, c->ev_join})
+      if (e) (void)hipEventDestroy(e);
+    (void)hipStreamDestroy(c->side);
+    delete c;
     return CHOL_ERR_HIP;
-  if (hipMalloc((void **)&c->sync, kSyncWords * sizeof(int)) != hipSuccess) return CHOL_ERR_HIP;
+  }
   g_ctx.push_back(c);
   *out = c;
   return CHOL_OK;
