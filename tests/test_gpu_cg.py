@@ -40,7 +40,7 @@ def rel(a, b):
 
 
 @pytest.mark.parametrize("n,k,tile", [(1000, 3, 128), (300, 1, 64), (130, 2, 128), (1, 1, 128),
-                                      (700, 16, 128), (200, 5, 64)])
+                                      (700, 16, 128), (200, 5, 64), (256, 2, 128), (64, 3, 64)])
 def test_cg_first_steps_match_oracle(n, k, tile):
     A, B = gp(n, k, seed=n + k)
     Ad, Bd = dev(A), dev(B)
@@ -85,6 +85,12 @@ def test_cg_converged_matches_oracle():
         # both within ||r|| / lambda_min (lambda_min >= noise 0.1) of the solution
         gap = np.linalg.norm(x[:, c] - xo[:, c])
         assert gap <= 2 * 2 * eps * np.linalg.norm(B[:, c]) / 0.1
+
+
+def test_cg_empty_system():
+    """n = 0: nothing to iterate; every column reports 0 steps and residual 0."""
+    res = P.cg_solve(P.colmajor_empty(0, 0), P.colmajor_empty(0, 2), eps=1e-8)
+    assert res.converged and res.iters == [0, 0] and res.relres == [0.0, 0.0]
 
 
 def test_cg_columns_are_independent_bitwise():
