@@ -117,3 +117,18 @@ def test_schedule_options_roundtrip():
             P.set_option(key, bad)
         P.set_option(key, old)
         assert P.get_option(key) == old
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """The bench runs on one GPU: any other count exits with status 2 and a
+    JSON error line, before touching a device."""
+    import json
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    for n in (2, 8):
+        r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", str(n)],
+                           capture_output=True, text=True, timeout=120)
+        assert r.returncode == 2
+        assert "one GPU" in json.loads(r.stdout.strip().splitlines()[-1])["error"]
