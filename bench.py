@@ -51,6 +51,20 @@ TRAFFIC = {"update_hip_sha256_16": "997d8b127706b215", "n": 32768, "bytes_per_la
            "algorithmic_bytes_per_launch": 2.790e9,
            "source": "profiles/update_f64_kernel_traffic_n32768.md"}
 
+# The same for the whole-triangle update of the mixed forms: FP32
+# (update_f32_kernel<0>, n = 65536, 124 launches) and FP16-scaled
+# (update_f16_wide_kernel, n = 131072, 62 launches).  Their algorithmic bytes
+# are estimates from the panel schedule (trailing region of N - (p + 2) w tile
+# rows after panel p; C tiles in FP32 read and written once, panel tiles read
+# once in FP32 or FP16).
+F32_TRAFFIC = {"update_hip_sha256_16": "997d8b127706b215", "n": 65536, "bytes_per_launch": 1.951e10,
+               "algorithmic_bytes_per_launch": 5.79e9,
+               "source": "profiles/update_f32_kernel_traffic_n65536.md"}
+F16_TRAFFIC = {"update_hip_sha256_16": "997d8b127706b215", "n": 131072, "bytes_per_launch": 5.094e10,
+               "algorithmic_bytes_per_launch": 2.23e10,
+               "source": "profiles/update_f16_wide_kernel_traffic_n131072.md"}
+TRAFFIC_BY_DTYPE = {"f64": TRAFFIC, "f32": F32_TRAFFIC, "f16": F16_TRAFFIC}
+
 # The same for the CG tile product (symv_tiles_kernel<128>) at n = 65536:
 # FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 per launch.
 CG_TRAFFIC = {"cg_hip_sha256_16": "6793051c70b70a14", "n": 65536, "bytes_per_launch": 17.49e9,
@@ -283,7 +297,7 @@ def main():
         roofline = {"bound": "mfma", "achieved": round(ach, 3), "peak": peak, "unit": "TFLOP/s",
                     "frac": round(ach / peak, 4), "traffic": measured_traffic(n, dtype),
                     "traffic_unit": "bytes per launch between L2 and the memory fabric (calibrated counters)",
-                    "algorithmic_bytes_per_launch": TRAFFIC["algorithmic_bytes_per_launch"]
+                    "algorithmic_bytes_per_launch": TRAFFIC_BY_DTYPE[dtype]["algorithmic_bytes_per_launch"]
                     if measured_traffic(n, dtype) else None,
                     "kernel": ("update_f64_kernel" if dtype == "f64" else "update_f32_kernel")
                     + ("<0> (Step-3 update of the trailing triangle)" if prof_mode == 2
@@ -470,7 +484,11 @@ def bench_fp16(args):
     if kl > 0 and kms > 0:
         ach = kfl / (kms * 1e-3) / 1e12
         roofline = {"bound": "mfma", "achieved": round(ach, 3), "peak": FP16_PEAK_TFLOPS,
-                    "unit": "TFLOP/s", "frac": round(ach / FP16_PEAK_TFLOPS, 4), "traffic": None,
+                    "unit": "TFLOP/s", "frac": round(ach / FP16_PEAK_TFLOPS, 4),
+                    "traffic": measured_traffic(n, "f16"),
+                    "traffic_unit": "bytes per launch between L2 and the memory fabric (calibrated counters)",
+                    "algorithmic_bytes_per_launch": F16_TRAFFIC["algorithmic_bytes_per_launch"]
+                    if measured_traffic(n, "f16") else None,
                     "kernel": "update_f16_wide_kernel (Step-3 update of the trailing triangle, 2 x 2 tiles per workgroup)",
                     "launches": kl, "avg_launch_us": round(kms * 1e3 / kl, 2),
                     "avg_launch_gflop": round(kfl / kl / 1e9, 4)}
@@ -490,17 +508,21 @@ def bench_fp16(args):
 
 
 def measured_traffic(n: int, dtype: str):
-    """Counter-measured bytes per launch of the bulk update, or None when the
-    workload or the kernel source differs from the one the counters saw."""
+    """Counter-measured bytes per launch of the bulk update (dtype f64, f32 or
+    f16: the update's operand precision), or None when the workload or the
+    kernel source differs from the one the counters saw."""
     import hashlib
+    rec = TRAFFIC_BY_DTYPE.get(dtype)
+    if rec is None:
+        return None
     src = os.path.join(ROOT, "paper_2605_13209_amd", "csrc", "update.hip")
     try:
         h = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
     except OSError:
         return None
-    if dtype != "f64" or n != TRAFFIC["n"] or h != TRAFFIC["update_hip_sha256_16"]:
+    if n != rec["n"] or h != rec["update_hip_sha256_16"]:
         return None
-    return TRAFFIC["bytes_per_launch"]
+    return rec["bytes_per_launch"]
 
 
 def measured_cg_traffic(n: int):
