@@ -401,3 +401,79 @@ def test_backward_error_estimate_is_unbiased():
     ratio = est / exact
     # ||A Z||^2 / k estimates ||A||_F^2 as well; both are chi-square-like
     assert 0.8 <= ratio <= 1.25, ratio
+
+
+# ------------------------------------- preconditioned CG (M = F F^T) ---
+
+def test_pcg_hand_worked_first_step():
+    # A = [[3, 2], [2, 6]], b = [2, -8], F = I (so M = I and x0 = M^-1 b = b).
+    # By hand: r0 = b - A x0 = [12, 36] = z0 = p0, rho = 1440, q = A p0 =
+    # [108, 240], p.q = 9936, alpha = 1440/9936 = 10/69, so
+    # x1 = x0 + alpha p0 = [86/23, -64/23] and r1 = [-84/23, 28/23] (r1.r0 = 0);
+    # the certificate with lam = 1 is |r1| / |x1| = sqrt(7840 / 11492).
+    # Two steps reach the exact solution [2, -2].  With recompute = 1 the
+    # periodic branch replaces r by b - A x after every step, which must not
+    # change these values beyond rounding.
+    A = np.array([[3.0, 2.0], [2.0, 6.0]])
+    b = np.array([2.0, -8.0])
+    for rc in (0, 1):
+        x1, it1, ce1, failed = oracle.pcg(np.eye(2), A, b, lam=1.0, tol=1e-300, max_iter=1, recompute=rc)
+        assert it1[0] == 1 and failed == 1
+        np.testing.assert_allclose(x1[:, 0], [86.0 / 23.0, -64.0 / 23.0], rtol=8 * U, atol=0)
+        assert abs(ce1[0] - np.sqrt(7840.0 / 11492.0)) <= 16 * U
+        x2, it2, ce2, failed = oracle.pcg(np.eye(2), A, b, lam=1.0, tol=1e-14, max_iter=5, recompute=rc)
+        assert failed == 0 and it2[0] == 2
+        np.testing.assert_allclose(x2[:, 0], [2.0, -2.0], rtol=16 * U, atol=16 * U)
+
+
+def _true_cert(A, b, x, lam):
+    r = b.astype(np.longdouble) - A.astype(np.longdouble) @ x.astype(np.longdouble)
+    xn = np.sqrt(np.sum(x.astype(np.longdouble) ** 2))
+    return float(np.sqrt(np.sum(r * r)) / (lam * xn))
+
+
+def test_pcg_recompute_branch_takes_true_residual():
+    """The periodic recomputation (every `recompute` iterations) replaces the
+    recurrence residual by b - A x: the certificate reported after a step
+    that recomputes equals the one of the true residual (numpy, long double).
+    Run far past the residual floor (80 steps, Jacobi preconditioner), the
+    recurrence residual without recomputation drifts many orders below the
+    true one; with the recomputation it stays on it."""
+    n, lam = 150, 0.05
+    X, B = gp_inputs.gp_problem(n, seed=23, k=1)
+    A = oracle.gp_assemble(X, 0.7, 1.0, lam)
+    F = np.diag(np.sqrt(np.diag(A)))  # M = diag(A): many iterations
+    b = B[:, 0]
+    for m in (3, 6, 9, 30):
+        x, it, ce, _ = oracle.pcg(F, A, B, lam=lam, tol=1e-300, max_iter=m, recompute=3)
+        assert it[0] == m
+        t = _true_cert(A, b, x[:, 0], lam)
+        assert abs(ce[0] - t) <= 1e-10 * t, (m, ce[0], t)
+    # early iterates do not depend on the recomputation beyond rounding
+    x3, _, _, _ = oracle.pcg(F, A, B, lam=lam, tol=1e-300, max_iter=9, recompute=3)
+    x0, _, _, _ = oracle.pcg(F, A, B, lam=lam, tol=1e-300, max_iter=9, recompute=0)
+    assert np.linalg.norm(x3 - x0) <= 1e-12 * np.linalg.norm(x0)
+    # far past the floor: recomputed residual on the true one, recurrence off it
+    m = 80
+    xr, _, cr, _ = oracle.pcg(F, A, B, lam=lam, tol=1e-300, max_iter=m, recompute=m)
+    tr = _true_cert(A, b, xr[:, 0], lam)
+    assert abs(cr[0] - tr) <= 1e-2 * tr, (cr[0], tr)
+    xn, _, cn, _ = oracle.pcg(F, A, B, lam=lam, tol=1e-300, max_iter=m, recompute=0)
+    tn = _true_cert(A, b, xn[:, 0], lam)
+    assert cn[0] <= 1e-3 * tn, (cn[0], tn)
+
+
+def test_pcg_small_recompute_interval_against_lapack():
+    """PCG with the true residual recomputed every second step converges to
+    LAPACK's solution; the certificate bounds the true error."""
+    n, lam = 300, 0.05
+    X, B = gp_inputs.gp_problem(n, seed=24, k=2)
+    A = oracle.gp_assemble(X, 0.7, 1.0, lam)
+    F = np.diag(np.sqrt(np.diag(A)))
+    xs, it, ce, failed = oracle.pcg(F, A, B, lam=lam, tol=1e-10, max_iter=2000, recompute=2)
+    assert failed == 0 and np.all(it > 4)
+    xnp = np.linalg.solve(A, B)
+    for c in range(2):
+        err = np.linalg.norm(xs[:, c] - xnp[:, c]) / np.linalg.norm(xnp[:, c])
+        assert err <= 1e-10, (c, err)
+        assert err <= ce[c] * np.linalg.norm(xs[:, c]) / np.linalg.norm(xnp[:, c]) * (1 + 1e-6) + 1e-15
