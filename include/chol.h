@@ -19,9 +19,9 @@
  *   and return after enqueueing, unless stated otherwise.
  * - Ownership: the caller allocates and frees all device memory.  The library
  *   never allocates device memory; it owns only the small host handle
- *   returned by chol_factor, plus one side stream and a few events per
- *   (device, caller stream) pair, created on first use and kept until the
- *   process ends.
+ *   returned by chol_factor (with one event for ordering solves), plus one
+ *   side stream and a few events per (device, caller stream) pair used by
+ *   chol_factor, created on first use and kept until the process ends.
  * - Threads: calls on different streams may run concurrently from different
  *   host threads; calls that share a stream must not overlap.
  * - Return value: CHOL_OK (0) on success; -i when argument i (1-based) is
@@ -74,12 +74,30 @@ extern "C" {
 
 typedef struct chol_factor_s *chol_handle;
 
+/* Fallbacks (bit flags in chol_refine_report.fallback_used and in
+ * chol_factor_fallback):
+ * CHOL_FALLBACK_PCG   iterative refinement stagnated (a right-hand side's
+ *                     correction failed to halve in two consecutive steps)
+ *                     and CG preconditioned with the factor finished the
+ *                     solve from the current iterate;
+ * CHOL_FALLBACK_SHIFT the FP16 form met a non-positive pivot and was
+ *                     refactored with the diagonal shift c * 2^-11 added to
+ *                     the scaled matrix (c = option "fp16_shift_c");
+ * CHOL_FALLBACK_FP32  the FP16 form failed (again) and an FP32 factor
+ *                     replaced it (chol_factor_precision then reports
+ *                     CHOL_FP32).                                           */
+#define CHOL_FALLBACK_PCG 1
+#define CHOL_FALLBACK_SHIFT 2
+#define CHOL_FALLBACK_FP32 4
+
 typedef struct {
-  int32_t iters;          /* corrections (IR) or iterations (PCG), max over RHS */
+  int32_t iters;          /* corrections (IR) plus iterations (PCG)            */
   int32_t converged;      /* 1 if every RHS met the stopping rule              */
   double cert;            /* max over RHS of the final error bound (see below) */
   double resid_norm;      /* max over RHS of ||b - A x||_2 at exit             */
   double time_ms;         /* host wall time of the call, including its sync    */
+  int32_t fallback_used;  /* CHOL_FALLBACK_* flags of the factor and the call  */
+  int32_t reserved;
 } chol_refine_report;
 
 /* ---- gp_assemble ------------------------------------------------------
@@ -128,6 +146,13 @@ int chol_tile_default(int64_t n, int precision);
  * info      : out, may be NULL.  If non-NULL the call synchronises the stream
  *             and stores the LAPACK-style info (0 = success).  If NULL the
  *             call is fully asynchronous; use chol_get_info later.
+ *             With CHOL_FP16_SCALED and info non-NULL, a non-positive pivot
+ *             is not returned at once: the factorisation is retried with a
+ *             diagonal shift, then as CHOL_FP32 (CHOL_FALLBACK_SHIFT /
+ *             CHOL_FALLBACK_FP32; chol_factor_fallback reports which), and
+ *             *info is the last attempt's.  The shifted factor is that of
+ *             A + s c 2^-11 I (s = the largest diagonal entry of A), which the
+ *             refinement then corrects.
  * Errors: -2 n < 0, -3 lda < max(1,n), -4 precision, -5 tile, -6 workspace
  * NULL or misaligned, -7 ws_bytes too small (also CHOL_ERR_WORKSPACE), -8 F
  * NULL.                                                                  */
@@ -158,6 +183,10 @@ int chol_factor_ex(const double *A, int64_t n, int64_t lda, int precision,
 /* Synchronises the factor's stream and reports info (0 = success).       */
 int chol_get_info(chol_handle F, int64_t *info);
 
+/* CHOL_FALLBACK_SHIFT / CHOL_FALLBACK_FP32 flags taken by chol_factor for
+ * this handle (0 = none; -1 for a NULL handle).                          */
+int chol_factor_fallback(chol_handle F);
+
 /* ---- chol_solve --------------------------------------------------------
  * B <- A^{-1} B using the factor only: forward substitution L Y = B, then
  * back substitution L^T X = Y (Fundamentals, "The Cholesky decomposition").
@@ -165,18 +194,29 @@ int chol_get_info(chol_handle F, int64_t *info);
  * tiles: block row i is b_i minus the products with the finished blocks,
  * times the inverted diagonal block, in one kernel launch per direction.
  * B : device, n x nrhs column-major FP64, ldb >= max(1, n), overwritten.
- * Uses a small per-(device, stream) synchronisation buffer that the library
- * allocates on the first call from a stream; when called under stream
- * capture, call it once on that stream before capturing.  Each wait between
- * workgroups is bounded (option "solve_spin_max"); should a bound ever run
- * out, the affected rows of B are set to NaN instead of hanging.
+ * The workgroups of a solve synchronise through words in the factor's
+ * workspace header, so solves with one factor are serialised: a solve
+ * issued on another stream than the previous solve with this factor waits
+ * for it (an event; not on a capturing stream, where the earlier solves must
+ * have been captured on that stream or have finished).  The first solve
+ * must be stream-ordered after chol_factor by the caller, as for any
+ * stream-ordered call.  Allocates nothing; may be captured into a graph.
+ * Each wait between workgroups is bounded (option "solve_spin_max"); should
+ * a bound ever run out, the affected rows of B are set to NaN instead of
+ * hanging.
  * Errors: CHOL_ERR_BAD_HANDLE, -2 B NULL with nrhs > 0, -3 nrhs < 0,
- * -4 ldb, CHOL_ERR_NOT_SPD if the factorisation reported info > 0.       */
+ * -4 ldb, CHOL_ERR_NOT_SPD if the factorisation is known (on the host) to
+ * have failed.  If it failed but the host has not read info yet (an
+ * asynchronous chol_factor), the call returns CHOL_OK and every entry of B
+ * becomes NaN: the kernels read the factor's info word.                  */
 int chol_solve(chol_handle F, double *B, int64_t nrhs, int64_t ldb,
                void *stream);
 
 /* ---- chol_refine_bytes -------------------------------------------------
- * Device workspace chol_refine_solve needs for nrhs right-hand sides.    */
+ * Device workspace chol_refine_solve needs for nrhs right-hand sides (the
+ * same for both methods, since refinement may fall back to PCG): five
+ * n x nrhs FP64 blocks plus 138 doubles per right-hand side plus 256 bytes.
+ * 0 for invalid arguments.                                                */
 size_t chol_refine_bytes(int64_t n, int64_t nrhs, int method);
 
 /* ---- chol_refine_solve -------------------------------------------------
@@ -192,14 +232,28 @@ size_t chol_refine_bytes(int64_t n, int64_t nrhs, int method);
  *          matrix: the noise variance).  With lam > 0 the stopping rule is
  *          the certificate ||r||_2 / (lam ||x||_2) <= tol / 2, a rigorous
  *          bound on the relative error ||x - x*|| / ||x||.  With lam <= 0 it
- *          is ||d||_2 <= tol ||x||_2 for the last correction d.
+ *          is ||d||_2 <= tol ||x||_2 for the last correction d (IR) or
+ *          ||r||_2 <= tol ||b||_2 (PCG).
  * B      : device, n x nrhs column-major FP64, ldb.  Not modified.
  * X      : device, n x nrhs column-major FP64, ldxs.  Output.
- * workspace: device, >= chol_refine_bytes(n, nrhs, method) bytes.
+ * workspace: device, 8-byte aligned, >= chol_refine_bytes(n, nrhs, method)
+ *          bytes.
  * rep    : out (host), may be NULL.
- * The call synchronises the stream once per iteration (it reads back one
- * norm per right-hand side).  Returns CHOL_ERR_NOT_CONVERGED if max_iter
- * is reached; X then holds the last iterate.                             */
+ * Both methods start from x0 = M^{-1} b and stop each right-hand side on
+ * its own (a finished column is left unchanged).  IR: x += M^{-1}(b - A x);
+ * a column whose correction fails to halve in two consecutive steps makes
+ * the call continue with PCG from the current iterate (CHOL_FALLBACK_PCG).
+ * PCG: the paper's CG algorithm with the preconditioner M = F F^T: q = A p,
+ * alpha = rho / p.q, x += alpha p, r -= alpha q; every `pcg_recompute`
+ * iterations (option, default 50; 0 = never) r is replaced by the true
+ * residual b - A x; a column that passes the stopping rule is confirmed on
+ * its true residual before it stops; z = M^{-1} r, rho' = r.z,
+ * p = z + (rho' / rho) p.  The scalars are computed on the device; the host
+ * reads back the squared norms of r and x (and of the IR correction) once
+ * per iteration to take the stopping decisions.  `iters` counts the IR
+ * corrections plus the PCG iterations against max_iter.
+ * Returns CHOL_ERR_NOT_CONVERGED if max_iter is reached; X then holds the
+ * last iterate.                                                          */
 int chol_refine_solve(chol_handle F, const double *A, int64_t lda,
                       const double *Xf, int64_t d, int64_t ldxf,
                       double lengthscale, double variance, double noise,
@@ -270,6 +324,11 @@ void chol_profile_reset(void);
  *                  (see chol_profile_read).
  * "solve_spin_max": polls allowed per wait inside chol_solve (default 2^20,
  *                  about a second; rows of a solve that runs out become NaN).
+ * "pcg_recompute": chol_refine_solve's PCG takes the true residual every
+ *                  this many iterations (default 50, the paper's periodic
+ *                  recomputation; 0 = never).
+ * "fp16_shift_c" : c of the FP16 form's shifted retry (default 8; 0 = go
+ *                  straight to the FP32 fallback).
  * "first_panel_width": tile columns of the first panel (1..16; 0 = the
  *                  panel width; default 0).  With lookahead the first
  *                  panel's tile columns are packed first and factored while

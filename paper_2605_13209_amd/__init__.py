@@ -9,6 +9,7 @@ call does, and raises if it is not built.
 """
 from ._native import (CG_MAX_RHS, CgResult, cg_solve, cg_workspace_bytes,  # noqa: F401
                       CHOL_FP16_SCALED, CHOL_FP32, CHOL_FP64, CholError, Factor, RefineResult,
+                      CHOL_FALLBACK_FP32, CHOL_FALLBACK_PCG, CHOL_FALLBACK_SHIFT,
                       chol_factor, chol_factor_bytes, chol_profile_read, chol_profile_reset, chol_factor_to_dense, chol_refine_bytes,
                       chol_refine_solve, chol_residual, chol_solve, chol_status_string, chol_tile_default,
                       colmajor_empty, get_option, gp_assemble, lib, set_option, to_colmajor)

@@ -42,7 +42,11 @@ class FactorOpts(ctypes.Structure):
 
 class RefineReport(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("converged", ctypes.c_int32), ("cert", ctypes.c_double),
-                ("resid_norm", ctypes.c_double), ("time_ms", ctypes.c_double)]
+                ("resid_norm", ctypes.c_double), ("time_ms", ctypes.c_double),
+                ("fallback_used", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+CHOL_FALLBACK_PCG, CHOL_FALLBACK_SHIFT, CHOL_FALLBACK_FP32 = 1, 2, 4
 
 
 EXPORTS = {
@@ -65,6 +69,7 @@ EXPORTS = {
     "chol_factor_n": (_i64, [_vp]),
     "chol_factor_tile": (_int, [_vp]),
     "chol_factor_precision": (_int, [_vp]),
+    "chol_factor_fallback": (_int, [_vp]),
     "chol_factor_free": (None, [_vp]),
     "chol_status_string": (ctypes.c_char_p, [_int]),
     "chol_set_option": (_int, [ctypes.c_char_p, _i64]),
@@ -194,6 +199,7 @@ class RefineResult:
     resid_norm: float
     time_ms: float
     status: int
+    fallback_used: int = 0
 
 
 class Factor:
@@ -206,6 +212,7 @@ class Factor:
         self.n = int(lib().chol_factor_n(handle))
         self.tile = int(lib().chol_factor_tile(handle))
         self.precision = int(lib().chol_factor_precision(handle))
+        self.fallback = int(lib().chol_factor_fallback(handle))
 
     @property
     def handle(self):
@@ -293,7 +300,8 @@ def chol_refine_solve(F: Factor, B: torch.Tensor, *, A: torch.Tensor | None = No
                                  workspace.numel() * workspace.element_size(), ctypes.byref(rep), _stream(stream))
     if rc not in (0, CHOL_ERR_NOT_CONVERGED) or (rc != 0 and raise_on_fail):
         _check(rc, "chol_refine_solve")
-    return RefineResult(X, rep.iters, bool(rep.converged), rep.cert, rep.resid_norm, rep.time_ms, rc)
+    return RefineResult(X, rep.iters, bool(rep.converged), rep.cert, rep.resid_norm, rep.time_ms, rc,
+                        rep.fallback_used)
 
 
 def chol_residual(A: torch.Tensor, X: torch.Tensor, B: torch.Tensor, out: torch.Tensor | None = None,

@@ -212,11 +212,38 @@ __global__ void axpby_kernel(const double *__restrict__ x, int64_t ldx, double *
 }
 
 __global__ void copy_kernel(const double *__restrict__ x, int64_t ldx, double *__restrict__ y,
-                            int64_t ldy, int64_t n, int64_t nrhs) {
+                            int64_t ldy, int64_t n, int64_t nrhs,
+                            const int32_t *__restrict__ mask) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= n * nrhs) return;
   const int64_t r = e % n, c = e / n;
+  if (mask && !mask[c]) return;
   y[r + c * ldy] = x[r + c * ldx];
+}
+
+// CG scalars, one thread per right-hand side (the preconditioned CG step:
+// alpha = rho / p.A p, beta = rho_new / rho).  pq holds p.q with q = -A p.
+// A zero or non-finite denominator gives a zero step instead of NaN.
+__global__ void pcg_alpha_kernel(const double *__restrict__ rho, const double *__restrict__ pq,
+                                 const int32_t *__restrict__ act, double *__restrict__ alpha,
+                                 int64_t nrhs) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= nrhs) return;
+  const double den = -pq[c];
+  alpha[c] = (act[c] && den != 0.0 && isfinite(den)) ? rho[c] / den : 0.0;
+}
+
+__global__ void pcg_beta_kernel(const double *__restrict__ rho_new, double *__restrict__ rho,
+                                const int32_t *__restrict__ act, double *__restrict__ beta,
+                                int64_t nrhs) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= nrhs) return;
+  if (!act[c]) {
+    beta[c] = 0.0;
+    return;
+  }
+  beta[c] = rho[c] != 0.0 ? rho_new[c] / rho[c] : 0.0;
+  rho[c] = rho_new[c];
 }
 
 }  // namespace
@@ -253,10 +280,29 @@ void launch_axpby(const double *x, int64_t ldx, double *y, int64_t ldy, int64_t 
 
 void launch_copy(const double *x, int64_t ldx, double *y, int64_t ldy, int64_t n, int64_t nrhs,
                  hipStream_t s) {
+  launch_copy_masked(x, ldx, y, ldy, n, nrhs, nullptr, s);
+}
+
+void launch_copy_masked(const double *x, int64_t ldx, double *y, int64_t ldy, int64_t n,
+                        int64_t nrhs, const int32_t *mask, hipStream_t s) {
   const int64_t tot = n * nrhs;
   if (tot <= 0) return;
   hipLaunchKernelGGL(copy_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, x, ldx, y,
-                     ldy, n, nrhs);
+                     ldy, n, nrhs, mask);
+}
+
+void launch_pcg_alpha(const double *rho, const double *pq, const int32_t *act, double *alpha,
+                      int64_t nrhs, hipStream_t s) {
+  if (nrhs <= 0) return;
+  hipLaunchKernelGGL(pcg_alpha_kernel, dim3((unsigned)((nrhs + 63) / 64)), dim3(64), 0, s, rho, pq,
+                     act, alpha, nrhs);
+}
+
+void launch_pcg_beta(const double *rho_new, double *rho, const int32_t *act, double *beta,
+                     int64_t nrhs, hipStream_t s) {
+  if (nrhs <= 0) return;
+  hipLaunchKernelGGL(pcg_beta_kernel, dim3((unsigned)((nrhs + 63) / 64)), dim3(64), 0, s, rho_new,
+                     rho, act, beta, nrhs);
 }
 
 }  // namespace chol

@@ -32,7 +32,14 @@ using namespace chol;
 
 namespace {
 
-constexpr size_t kHeader = 256;  // info word + reserved, at the start of the workspace
+// Start of the factor workspace: the info word (offset 0), the largest
+// diagonal entry for the FP16 form's scaling (offset 64), and the solves'
+// synchronisation words (offset kSolveSyncOff, kSolveSyncWords ints: an
+// abort word and per-chunk progress counters, cleared by a kernel before
+// every solve).
+constexpr size_t kHeader = 512;
+constexpr size_t kSolveSyncOff = 256;
+constexpr int64_t kSolveSyncWords = 64;
 
 struct Options {
   std::atomic<int64_t> panel_width{0};  // 0: automatic
@@ -44,22 +51,20 @@ struct Options {
   std::atomic<int64_t> first_panel_width{0};  // tile columns of the first panel (0 = the panel width)
   std::atomic<int64_t> f16_wide{1};  // FP16 whole-triangle update with 2 x 2 tiles per workgroup
   std::atomic<int64_t> solve_spin_max{1 << 20};  // bound of each wait inside a solve
+  std::atomic<int64_t> pcg_recompute{50};  // PCG: true residual every this many iterations
+  std::atomic<int64_t> fp16_shift_c{8};    // FP16 retry: diagonal shift c * 2^-11 (0 = no retry)
 };
 Options g_opt;
 
 // Lookahead resources: a side stream and four events per (device, caller
 // stream), created on first use and kept until the process ends, so that
 // factorisations issued concurrently on different caller streams (e.g. by
-// the serving loop's worker threads) never share them.
-// The same context holds the solves' synchronisation words (an abort flag
-// and per-chunk progress counters, cleared by a kernel before every solve).
-constexpr int64_t kSyncWords = 4096;
+// the serving loop's worker threads) never share them.  No device memory.
 struct SideCtx {
   int device = -1;
   hipStream_t caller = nullptr;
   hipStream_t side = nullptr;
   hipEvent_t ev_fork = nullptr, ev_panel = nullptr, ev_bulk = nullptr, ev_join = nullptr;
-  int *sync = nullptr;  // kSyncWords ints of device memory
 };
 std::mutex g_ctx_mu;
 std::vector<SideCtx *> g_ctx;
@@ -84,8 +89,7 @@ int get_ctx(hipStream_t caller, SideCtx **out) {
   if (hipEventCreateWithFlags(&c->ev_fork, fl) != hipSuccess ||
       hipEventCreateWithFlags(&c->ev_panel, fl) != hipSuccess ||
       hipEventCreateWithFlags(&c->ev_bulk, fl) != hipSuccess ||
-      hipEventCreateWithFlags(&c->ev_join, fl) != hipSuccess ||
-      hipMalloc((void **)&c->sync, kSyncWords * sizeof(int)) != hipSuccess) {
+      hipEventCreateWithFlags(&c->ev_join, fl) != hipSuccess) {
     // a half-built context is released, so a later call can try again
     for (hipEvent_t e : {c->ev_fork, c->ev_panel, c->ev_bulk, c->ev_join})
       if (e) (void)hipEventDestroy(e);
@@ -215,9 +219,23 @@ struct chol_factor_s {
   void *dinv = nullptr;  // inverted diagonal blocks L_cc^{-T} (the solves)
   void *p16 = nullptr;   // CHOL_FP16_SCALED: two FP16 panel buffers (alternating panels)
   int64_t *d_info = nullptr;
-  double scale = 1.0;  // CHOL_FP16_SCALED: the factor of A / scale is stored
+  int *sync = nullptr;   // the solves' synchronisation words (workspace header)
+  double scale = 1.0;  // CHOL_FP16_SCALED: the factor of A / scale (+ shift I) is stored
+  double shift = 0.0;  // CHOL_FP16_SCALED retry: diagonal shift added to A / scale
+  int fallback = 0;    // CHOL_FALLBACK_SHIFT / CHOL_FALLBACK_FP32 taken by chol_factor
   hipStream_t stream = nullptr;
   int64_t info = -1;  // host copy once known
+  // Solves share the synchronisation words: a solve on another stream than
+  // the previous one waits for it (event recorded after every solve).
+  // The mutex makes that check, the launches and the record one step when
+  // several host threads solve with the handle.
+  std::mutex solve_mu;
+  hipEvent_t ev_solve = nullptr;
+  hipStream_t last_solve = nullptr;
+  bool solved = false;
+  ~chol_factor_s() {
+    if (ev_solve) (void)hipEventDestroy(ev_solve);
+  }
 };
 
 #define HIP_OK(x)                              \
@@ -272,6 +290,12 @@ int chol_set_option(const char *key, int64_t value) {
     if (value < 0 || value > 1) return -2;
     g_opt.f16_wide = value;
     set_f16_wide((int)value);
+  } else if (!strcmp(key, "pcg_recompute")) {
+    if (value < 0 || value > (int64_t)1 << 30) return -2;
+    g_opt.pcg_recompute = value;
+  } else if (!strcmp(key, "fp16_shift_c")) {
+    if (value < 0 || value > 1024) return -2;
+    g_opt.fp16_shift_c = value;
   } else {
     return -1;
   }
@@ -289,6 +313,8 @@ int64_t chol_get_option(const char *key) {
   if (!strcmp(key, "first_panel_width")) return g_opt.first_panel_width;
   if (!strcmp(key, "f16_wide")) return g_opt.f16_wide;
   if (!strcmp(key, "solve_spin_max")) return g_opt.solve_spin_max;
+  if (!strcmp(key, "pcg_recompute")) return g_opt.pcg_recompute;
+  if (!strcmp(key, "fp16_shift_c")) return g_opt.fp16_shift_c;
   return -1;
 }
 
@@ -384,6 +410,7 @@ static void factor_panel(chol_factor_s *F, size_t p, int64_t c0, int64_t c1, int
 // Panels: the first w0 tile columns, then w at a time.
 static int enqueue_factor(chol_factor_s *F, SideCtx *ctx, const double *A, int64_t lda, int st,
                           double pack_scale, int64_t w, int64_t w0, int S, bool la) {
+  const double sh = F->shift;
   const int64_t N = F->N, n = F->n;
   const int b = F->b;
   const int fp16 = F->precision == CHOL_FP16_SCALED;
@@ -396,7 +423,7 @@ static int enqueue_factor(chol_factor_s *F, SideCtx *ctx, const double *A, int64
   const size_t P = pb.size() - 1;
   launch_clear_i64(F->d_info, 1, s);
   if (!la) {
-    launch_pack(A, n, lda, F->tiles, st, b, N, pack_scale, s);
+    launch_pack(A, n, lda, F->tiles, st, b, N, pack_scale, s, 0, -1, sh);
     for (size_t p = 0; p < P; ++p) {
       const int64_t c0 = pb[p], c1 = pb[p + 1];
       factor_panel(F, p, c0, c1, st, s);
@@ -408,11 +435,11 @@ static int enqueue_factor(chol_factor_s *F, SideCtx *ctx, const double *A, int64
     // the first panel's tile columns are packed first and factored on the
     // side stream while the main stream packs the rest
     hipStream_t q = ctx->side;
-    launch_pack(A, n, lda, F->tiles, st, b, N, pack_scale, s, 0, pb[1]);
+    launch_pack(A, n, lda, F->tiles, st, b, N, pack_scale, s, 0, pb[1], sh);
     HIP_OK(hipEventRecord(ctx->ev_fork, s));
     HIP_OK(hipStreamWaitEvent(q, ctx->ev_fork, 0));
     factor_panel(F, 0, 0, pb[1], st, q);
-    launch_pack(A, n, lda, F->tiles, st, b, N, pack_scale, s, pb[1], N);
+    launch_pack(A, n, lda, F->tiles, st, b, N, pack_scale, s, pb[1], N, sh);
     HIP_OK(hipEventRecord(ctx->ev_bulk, s));  // everything packed
     for (size_t p = 0; p < P; ++p) {
       const int64_t c0 = pb[p], c1 = pb[p + 1];   // current panel [c0, c1)
@@ -478,6 +505,7 @@ int chol_factor_ex(const double *A, int64_t n, int64_t lda, int precision,
   F->precision = precision;
   (void)hipGetDevice(&F->device);
   F->d_info = (int64_t *)workspace;
+  F->sync = (int *)((char *)workspace + kSolveSyncOff);
   F->tiles = (char *)workspace + kHeader;
   F->dinv = (char *)F->tiles + (size_t)tile_count(F->N) * (size_t)tile * tile * esize_of(precision);
   if (precision == CHOL_FP16_SCALED)
@@ -593,6 +621,35 @@ int chol_factor_ex(const double *A, int64_t n, int64_t lda, int precision,
   if (info) {
     rc = chol_get_info(F, info);
     if (rc) return rc;
+    // FP16 form, non-positive pivot: retry once with the diagonal shift
+    // c u_16 I added to the scaled matrix, then fall back to an FP32 factor
+    // (the FP32 factor needs less workspace than the FP16 form).
+    if (*info > 0 && precision == CHOL_FP16_SCALED) {
+      const int64_t c = g_opt.fp16_shift_c.load();
+      if (c > 0) {
+        F->shift = (double)c * 0x1p-11;
+        F->fallback |= CHOL_FALLBACK_SHIFT;
+        F->info = -1;
+        rc = enqueue_factor(F, ctx, A, lda, st, pack_scale, w, w0, S, la);
+        if (rc) return rc;
+        rc = chol_get_info(F, info);
+        if (rc) return rc;
+      }
+      if (*info > 0) {
+        F->precision = CHOL_FP32;
+        F->scale = 1.0;
+        F->shift = 0.0;
+        F->p16 = nullptr;
+        F->fallback |= CHOL_FALLBACK_FP32;
+        F->info = -1;
+        const int64_t w32 = std::min<int64_t>(w, 8);
+        rc = enqueue_factor(F, ctx, A, lda, STORE_F32, 1.0, w32, std::min(w0, w32), S,
+                            la_opt != 0 && N > w32);
+        if (rc) return rc;
+        rc = chol_get_info(F, info);
+        if (rc) return rc;
+      }
+    }
   }
   return CHOL_OK;
 }
@@ -612,6 +669,7 @@ int chol_get_info(chol_handle F, int64_t *info) {
 int64_t chol_factor_n(chol_handle F) { return F ? F->n : -1; }
 int chol_factor_tile(chol_handle F) { return F ? F->b : -1; }
 int chol_factor_precision(chol_handle F) { return F ? F->precision : -1; }
+int chol_factor_fallback(chol_handle F) { return F ? F->fallback : -1; }
 
 void chol_factor_free(chol_handle F) { delete F; }
 
@@ -624,12 +682,21 @@ int chol_solve(chol_handle F, double *B, int64_t nrhs, int64_t ldb, void *stream
   hipStream_t s = (hipStream_t)stream;
   const int st = store_of(F->precision);
   if (F->n == 0 || nrhs == 0) return CHOL_OK;
-  SideCtx *ctx = nullptr;
-  const int rc = get_ctx(s, &ctx);
-  if (rc) return rc;
-  launch_solve(F->tiles, F->dinv, st, F->b, F->N, F->n, B, ldb, nrhs, ctx->sync, kSyncWords,
-               (int)g_opt.solve_spin_max.load(), s);
+  // order after the previous solve with this factor if it ran on another
+  // stream (both use the synchronisation words in the factor's workspace);
+  // skipped on a capturing stream, whose earlier solves are on that stream
+  std::lock_guard<std::mutex> lk(F->solve_mu);
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  HIP_OK(hipStreamIsCapturing(s, &cap));
+  if (F->solved && F->last_solve != s && cap == hipStreamCaptureStatusNone)
+    HIP_OK(hipStreamWaitEvent(s, F->ev_solve, 0));
+  launch_solve(F->tiles, F->dinv, st, F->b, F->N, F->n, B, ldb, nrhs, F->sync, kSolveSyncWords,
+               (int)g_opt.solve_spin_max.load(), F->d_info, s);
   if (F->scale != 1.0) launch_scale(B, F->n, ldb, nrhs, 1.0 / F->scale, s);
+  if (!F->ev_solve) HIP_OK(hipEventCreateWithFlags(&F->ev_solve, hipEventDisableTiming));
+  HIP_OK(hipEventRecord(F->ev_solve, s));
+  F->last_solve = s;
+  F->solved = true;
   return hipGetLastError() == hipSuccess ? CHOL_OK : CHOL_ERR_HIP;
 }
 
@@ -638,7 +705,7 @@ int chol_factor_to_dense(chol_handle F, double *L, int64_t ldl, void *stream) {
   if (F->n > 0 && !L) return -2;
   if (ldl < (F->n > 1 ? F->n : 1)) return -3;
   launch_unpack(F->tiles, store_of(F->precision), F->b, F->N, F->n, std::sqrt(F->scale), L, ldl,
-                (hipStream_t)stream);
+                F->d_info, (hipStream_t)stream);
   return hipGetLastError() == hipSuccess ? CHOL_OK : CHOL_ERR_HIP;
 }
 
@@ -657,16 +724,227 @@ int chol_residual(const double *A, int64_t lda, int64_t n, const double *X, int6
   return hipGetLastError() == hipSuccess ? CHOL_OK : CHOL_ERR_HIP;
 }
 
+
 // ---------------------------------------------------------- refinement ----
-// Workspace layout (FP64, each n x nrhs block with leading dimension n):
-//   r, d [IR];  r, z, p, q [PCG];  then scalars: 8 arrays of nrhs doubles and
-//   the dot-product partials (128 * nrhs doubles).
+// Workspace layout: five n x nrhs FP64 blocks (leading dimension n)
+//   r (residual), z (IR correction / PCG preconditioned residual), p, q = -A p,
+//   t (true residual at a check),
+// then per right-hand side: rr, xx, dd (squared norms of r, x and the last
+// correction, read back together), rho, rho_new, pq, alpha, beta, bb (b.b);
+// two int32 masks (active columns, columns being confirmed); and the
+// dot-product partials (128 per right-hand side).
 size_t chol_refine_bytes(int64_t n, int64_t nrhs, int method) {
-  if (n < 0 || nrhs < 0) return 0;
-  const int64_t blocks = method == CHOL_REFINE_PCG ? 4 : 2;
+  if (n < 0 || nrhs < 0 || (method != CHOL_REFINE_IR && method != CHOL_REFINE_PCG)) return 0;
   const size_t vec = (size_t)n * (size_t)nrhs * sizeof(double);
-  return blocks * vec + (size_t)(8 + 128) * (size_t)nrhs * sizeof(double) + 256;
+  return 5 * vec + (size_t)(9 + 1 + 128) * (size_t)nrhs * sizeof(double) + 256;
 }
+
+namespace {
+
+// One call of chol_refine_solve: the iterative refinement of classic
+// mixed-precision solvers (x <- x + M^{-1}(b - A x), M = F F^T) and the
+// paper's CG algorithm preconditioned with M, on device vectors; the host
+// reads back three squared norms per right-hand side per iteration and
+// decides the stopping tests, the scalars of CG stay on the device.
+struct Refiner {
+  chol_factor_s *F;
+  const double *A;
+  int64_t lda;
+  const double *Xf;
+  int64_t d, ldxf;
+  double two_l2, var, noise;
+  const double *B;
+  int64_t ldb;
+  double *X;
+  int64_t ldx, n, k;
+  double tol, lam;
+  bool certify;
+  hipStream_t s;
+  double *r, *z, *p, *q, *t;
+  double *nrm;  // rr[k], xx[k], dd[k]
+  double *rho, *rho_new, *pq, *alpha, *beta, *bb;
+  int32_t *act, *msk;
+  double *partial;
+  std::vector<double> h_nrm, h_bb, cert;
+  std::vector<int32_t> h_act, h_msk;
+  int iters = 0;
+  int fallback = 0;
+  int rc = CHOL_OK;
+
+  void setup(void *ws) {
+    const size_t vec = (size_t)n * (size_t)k;
+    r = (double *)ws;
+    z = r + vec;
+    p = z + vec;
+    q = p + vec;
+    t = q + vec;
+    nrm = t + vec;
+    rho = nrm + 3 * k;
+    rho_new = rho + k;
+    pq = rho_new + k;
+    alpha = pq + k;
+    beta = alpha + k;
+    bb = beta + k;
+    act = (int32_t *)(bb + k);
+    msk = act + k;
+    partial = (double *)act + k;  // k doubles hold the two int32 masks
+    h_nrm.assign(3 * k, 0.0);
+    h_bb.assign(k, 0.0);
+    cert.assign(k, INFINITY);
+    h_act.assign(k, 1);
+    h_msk.assign(k, 0);
+  }
+  bool ok(hipError_t e) {
+    if (e != hipSuccess && rc == CHOL_OK) rc = CHOL_ERR_HIP;
+    return rc == CHOL_OK;
+  }
+  // out = B - A x (or -A x when rhs is false)
+  void residual(const double *x, int64_t ldxx, double *out, bool rhs = true) {
+    const double *Bm = rhs ? B : nullptr;
+    if (A)
+      launch_symm_residual(A, lda, n, x, ldxx, Bm, ldb, out, n, k, s);
+    else
+      launch_gp_residual(Xf, n, d, ldxf, two_l2, var, noise, x, ldxx, Bm, ldb, out, n, k, s);
+  }
+  void msolve(double *v) {
+    const int e = chol_solve(F, v, k, n, s);
+    if (e && rc == CHOL_OK) rc = e;
+  }
+  // rr = r.r, xx = x.x (and dd = z.z), read back; one synchronisation
+  bool norms(bool with_dd) {
+    launch_col_dot(r, n, r, n, n, k, nrm, partial, s);
+    launch_col_dot(X, ldx, X, ldx, n, k, nrm + k, partial, s);
+    if (with_dd) launch_col_dot(z, n, z, n, n, k, nrm + 2 * k, partial, s);
+    if (!ok(hipMemcpyAsync(h_nrm.data(), nrm, (with_dd ? 3 : 2) * k * sizeof(double),
+                           hipMemcpyDeviceToHost, s)))
+      return false;
+    return ok(hipStreamSynchronize(s));
+  }
+  double cert_of(int64_t c) const {
+    const double rn = std::sqrt(h_nrm[c]), xn = std::sqrt(h_nrm[k + c]);
+    const double ce = certify ? rn / (lam * xn) : rn / std::sqrt(h_bb[c]);
+    return std::isnan(ce) ? INFINITY : ce;
+  }
+  // the stopping test on the current r and x: the certificate
+  // ||r|| / (lam ||x||) <= tol / 2, or without a bound on the smallest
+  // eigenvalue ||r|| <= tol ||b|| (PCG; IR tests its correction)
+  bool passes(int64_t c) const { return cert[c] <= (certify ? 0.5 * tol : tol); }
+  bool upload(int32_t *dst, const std::vector<int32_t> &src) {
+    return ok(hipMemcpyAsync(dst, src.data(), k * sizeof(int32_t), hipMemcpyHostToDevice, s));
+  }
+  int active_count() const {
+    int a = 0;
+    for (int64_t c = 0; c < k; ++c) a += h_act[c];
+    return a;
+  }
+
+  // Iterative refinement.  Returns true when PCG should take over (a column
+  // whose correction failed to halve twice in a row: stagnation).
+  bool run_ir(int max_iter) {
+    std::vector<double> dprev(k, INFINITY);
+    std::vector<int> stall(k, 0);
+    if (!upload(act, h_act)) return false;
+    for (;;) {
+      residual(X, ldx, r);
+      if (!norms(iters > 0)) return false;
+      bool changed = false;
+      for (int64_t c = 0; c < k; ++c) {
+        if (!h_act[c]) continue;
+        if (certify) {
+          cert[c] = cert_of(c);
+          if (cert[c] <= 0.5 * tol) {
+            h_act[c] = 0;
+            changed = true;
+            continue;
+          }
+        }
+        if (iters > 0) {
+          const double dn = std::sqrt(h_nrm[2 * k + c]), xn = std::sqrt(h_nrm[k + c]);
+          if (!certify) {
+            cert[c] = std::isnan(dn / xn) ? INFINITY : dn / xn;
+            if (dn <= tol * xn) {
+              h_act[c] = 0;
+              changed = true;
+              continue;
+            }
+          }
+          stall[c] = dn > 0.5 * dprev[c] ? stall[c] + 1 : 0;
+          dprev[c] = dn;
+        }
+      }
+      if (active_count() == 0 || iters >= max_iter) return false;
+      for (int64_t c = 0; c < k; ++c)
+        if (h_act[c] && stall[c] >= 2) return true;
+      if (changed && !upload(act, h_act)) return false;
+      launch_copy(r, n, z, n, n, k, s);
+      msolve(z);
+      launch_axpby(z, n, X, ldx, n, k, nullptr, 1.0, nullptr, act, s);  // x += d
+      ++iters;
+      if (rc) return false;
+    }
+  }
+
+  // CG preconditioned with M = F F^T from the current x, for the active
+  // columns, with the true residual every `recompute` iterations and before
+  // a column is declared converged.
+  void run_pcg(int max_iter, int64_t recompute) {
+    residual(X, ldx, r);
+    if (!norms(false)) return;
+    for (int64_t c = 0; c < k; ++c)
+      if (h_act[c]) {
+        cert[c] = cert_of(c);
+        if (passes(c)) h_act[c] = 0;
+      }
+    if (active_count() == 0 || !upload(act, h_act)) return;
+    launch_copy(r, n, z, n, n, k, s);
+    msolve(z);
+    launch_copy(z, n, p, n, n, k, s);
+    launch_col_dot(r, n, z, n, n, k, rho, partial, s);
+    for (int64_t it = 1; iters < max_iter; ++it) {
+      residual(p, n, q, false);                                        // q = -A p
+      launch_col_dot(p, n, q, n, n, k, pq, partial, s);
+      launch_pcg_alpha(rho, pq, act, alpha, k, s);                     // rho / p.Ap
+      launch_axpby(p, n, X, ldx, n, k, alpha, 1.0, nullptr, act, s);  // x += alpha p
+      launch_axpby(q, n, r, n, n, k, alpha, 1.0, nullptr, act, s);     // r -= alpha A p
+      ++iters;
+      if (recompute > 0 && it % recompute == 0) {
+        residual(X, ldx, t);
+        launch_copy_masked(t, n, r, n, n, k, act, s);
+      }
+      if (!norms(false)) return;
+      bool any = false;
+      for (int64_t c = 0; c < k; ++c) {
+        h_msk[c] = 0;
+        if (!h_act[c]) continue;
+        cert[c] = cert_of(c);
+        if (passes(c)) h_msk[c] = 1, any = true;
+      }
+      if (any) {
+        // confirm on the true residual; a column that fails keeps it as r
+        residual(X, ldx, t);
+        if (!upload(msk, h_msk)) return;
+        launch_copy_masked(t, n, r, n, n, k, msk, s);
+        if (!norms(false)) return;
+        bool changed = false;
+        for (int64_t c = 0; c < k; ++c)
+          if (h_msk[c]) {
+            cert[c] = cert_of(c);
+            if (passes(c)) h_act[c] = 0, changed = true;
+          }
+        if (active_count() == 0) return;
+        if (changed && !upload(act, h_act)) return;
+      }
+      launch_copy(r, n, z, n, n, k, s);
+      msolve(z);
+      launch_col_dot(r, n, z, n, n, k, rho_new, partial, s);
+      launch_pcg_beta(rho_new, rho, act, beta, k, s);                 // beta; rho <- rho_new
+      launch_axpby(z, n, p, n, n, k, nullptr, 1.0, beta, act, s);     // p = z + beta p
+      if (rc) return;
+    }
+  }
+};
+
+}  // namespace
 
 int chol_refine_solve(chol_handle F, const double *A, int64_t lda, const double *Xf, int64_t d,
                       int64_t ldxf, double lengthscale, double variance, double noise,
@@ -685,7 +963,8 @@ int chol_refine_solve(chol_handle F, const double *A, int64_t lda, const double 
   if (!(tol > 0.0)) return -15;
   if (max_iter < 0) return -16;
   if (method != CHOL_REFINE_IR && method != CHOL_REFINE_PCG) return -17;
-  if (ws_bytes < chol_refine_bytes(n, nrhs, method) || (!workspace && nrhs > 0))
+  if (ws_bytes < chol_refine_bytes(n, nrhs, method) || (!workspace && nrhs > 0) ||
+      ((uintptr_t)workspace & 7))
     return CHOL_ERR_WORKSPACE;
   if (F->info < 0) {
     int64_t inf;
@@ -695,161 +974,65 @@ int chol_refine_solve(chol_handle F, const double *A, int64_t lda, const double 
   if (F->info > 0) return CHOL_ERR_NOT_SPD;
   if (rep) memset(rep, 0, sizeof(*rep));
   if (n == 0 || nrhs == 0) {
-    if (rep) rep->converged = 1;
+    if (rep) rep->converged = 1, rep->fallback_used = F->fallback;
     return CHOL_OK;
   }
-  hipStream_t s = (hipStream_t)stream;
-  const size_t vec = (size_t)n * (size_t)nrhs;
-  double *r = (double *)workspace;
-  double *dv = r + vec;  // IR correction / PCG z
-  double *pv = dv + vec;  // PCG only
-  double *qv = pv + vec;  // PCG only
-  double *scal = (double *)workspace + (method == CHOL_REFINE_PCG ? 4 : 2) * vec;
-  double *rr = scal, *xx = scal + nrhs, *rho = scal + 2 * nrhs, *rho_new = scal + 3 * nrhs,
-         *pq = scal + 4 * nrhs, *alpha = scal + 5 * nrhs, *beta = scal + 6 * nrhs;
-  double *partial = scal + 8 * nrhs;
-  const double lam = noise;
-  const bool certify = lam > 0.0;
-
-  auto residual = [&](const double *x, double *out) {
-    if (A)
-      launch_symm_residual(A, lda, n, x, ldxs, B, ldb, out, n, nrhs, s);
-    else
-      launch_gp_residual(Xf, n, d, ldxf, 2.0 * lengthscale * lengthscale, variance, noise, x,
-                         ldxs, B, ldb, out, n, nrhs, s);
-  };
-  auto msolve = [&](double *v) { chol_solve(F, v, nrhs, n, s); };
-  std::vector<double> h_rr(nrhs), h_xx(nrhs), h_a(nrhs), h_b(nrhs);
-  auto fetch_norms = [&](const double *v, const double *x) -> int {
-    launch_col_dot(v, n, v, n, n, nrhs, rr, partial, s);
-    launch_col_dot(x, ldxs, x, ldxs, n, nrhs, xx, partial + 64 * 0, s);
-    if (hipMemcpyAsync(h_rr.data(), rr, nrhs * sizeof(double), hipMemcpyDeviceToHost, s) !=
-            hipSuccess ||
-        hipMemcpyAsync(h_xx.data(), xx, nrhs * sizeof(double), hipMemcpyDeviceToHost, s) !=
-            hipSuccess ||
-        hipStreamSynchronize(s) != hipSuccess)
-      return CHOL_ERR_HIP;
-    return CHOL_OK;
-  };
-
-  // x0 = F^-T F^-1 b
-  launch_copy(B, ldb, X, ldxs, n, nrhs, s);
-  msolve(X);
-  int iters = 0;
-  bool conv = false;
-  double cert_max = INFINITY, res_max = INFINITY;
-  auto certify_now = [&](const double *res) -> int {
-    int rc = fetch_norms(res, X);
-    if (rc) return rc;
-    cert_max = 0.0;
-    res_max = 0.0;
-    for (int64_t c = 0; c < nrhs; ++c) {
-      const double rn = std::sqrt(h_rr[c]), xn = std::sqrt(h_xx[c]);
-      res_max = std::fmax(res_max, rn);
-      const double ce = certify ? rn / (lam * xn) : INFINITY;
-      cert_max = std::fmax(cert_max, std::isnan(ce) ? INFINITY : ce);
-    }
-    return CHOL_OK;
-  };
-
+  Refiner R{};
+  R.F = F;
+  R.A = A;
+  R.lda = lda;
+  R.Xf = Xf;
+  R.d = d;
+  R.ldxf = ldxf;
+  R.two_l2 = 2.0 * lengthscale * lengthscale;
+  R.var = variance;
+  R.noise = noise;
+  R.B = B;
+  R.ldb = ldb;
+  R.X = X;
+  R.ldx = ldxs;
+  R.n = n;
+  R.k = nrhs;
+  R.tol = tol;
+  R.lam = noise;
+  R.certify = noise > 0.0;
+  R.s = (hipStream_t)stream;
+  R.setup(workspace);
+  if (!R.certify) {
+    // ||b|| for the relative-residual test of PCG without an eigenvalue bound
+    launch_col_dot(B, ldb, B, ldb, n, nrhs, R.bb, R.partial, R.s);
+    if (!R.ok(hipMemcpyAsync(R.h_bb.data(), R.bb, nrhs * sizeof(double), hipMemcpyDeviceToHost,
+                             R.s)))
+      return R.rc;
+  }
+  // x0 = M^{-1} b
+  launch_copy(B, ldb, X, ldxs, n, nrhs, R.s);
+  R.msolve(X);
+  if (R.rc) return R.rc;
   if (method == CHOL_REFINE_IR) {
-    for (;;) {
-      residual(X, r);
-      int rc = certify_now(r);
-      if (rc) return rc;
-      if (certify && cert_max <= 0.5 * tol) {
-        conv = true;
-        break;
-      }
-      if (iters >= max_iter) break;
-      launch_copy(r, n, dv, n, n, nrhs, s);
-      msolve(dv);
-      launch_axpby(dv, n, X, ldxs, n, nrhs, nullptr, 1.0, nullptr, nullptr, s);
-      ++iters;
-      if (!certify) {
-        // ||d|| <= tol ||x||
-        rc = fetch_norms(dv, X);
-        if (rc) return rc;
-        bool all = true;
-        for (int64_t c = 0; c < nrhs; ++c)
-          all = all && std::sqrt(h_rr[c]) <= tol * std::sqrt(h_xx[c]);
-        cert_max = 0.0;
-        for (int64_t c = 0; c < nrhs; ++c)
-          cert_max = std::fmax(cert_max, std::sqrt(h_rr[c]) / std::sqrt(h_xx[c]));
-        if (all) {
-          conv = true;
-          break;
-        }
-      }
+    if (R.run_ir(max_iter) && R.rc == CHOL_OK) {
+      R.fallback |= CHOL_FALLBACK_PCG;
+      R.run_pcg(max_iter, g_opt.pcg_recompute.load());
     }
   } else {
-    // PCG with M = F F^T, starting from x0 = M^-1 b.
-    double *z = dv;
-    residual(X, r);
-    int rc = certify_now(r);
-    if (rc) return rc;
-    if (certify && cert_max <= 0.5 * tol) conv = true;
-    if (!conv) {
-      launch_copy(r, n, z, n, n, nrhs, s);
-      msolve(z);
-      launch_copy(z, n, pv, n, n, nrhs, s);
-      launch_col_dot(r, n, z, n, n, nrhs, rho, partial, s);
-      std::vector<double> h_rho(nrhs), h_pq(nrhs);
-      HIP_OK(hipMemcpyAsync(h_rho.data(), rho, nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
-      HIP_OK(hipStreamSynchronize(s));
-      while (iters < max_iter) {
-        // q = -(A p): the residual kernels with no right-hand side
-        if (A)
-          launch_symm_residual(A, lda, n, pv, n, nullptr, n, qv, n, nrhs, s);
-        else
-          launch_gp_residual(Xf, n, d, ldxf, 2.0 * lengthscale * lengthscale, variance, noise, pv,
-                             n, nullptr, n, qv, n, nrhs, s);
-        launch_col_dot(pv, n, qv, n, n, nrhs, pq, partial, s);
-        HIP_OK(hipMemcpyAsync(h_pq.data(), pq, nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
-        HIP_OK(hipStreamSynchronize(s));
-        for (int64_t c = 0; c < nrhs; ++c) {
-          const double den = -h_pq[c];
-          h_a[c] = (den != 0.0 && std::isfinite(den)) ? h_rho[c] / den : 0.0;
-        }
-        HIP_OK(hipMemcpyAsync(alpha, h_a.data(), nrhs * sizeof(double), hipMemcpyHostToDevice, s));
-        launch_axpby(pv, n, X, ldxs, n, nrhs, alpha, 1.0, nullptr, nullptr, s);  // x += a p
-        launch_axpby(qv, n, r, n, n, nrhs, alpha, 1.0, nullptr, nullptr, s);     // r += a q = r - a A p
-        ++iters;
-        rc = certify_now(r);
-        if (rc) return rc;
-        if (certify && cert_max <= 0.5 * tol) {
-          // confirm on the true residual
-          residual(X, r);
-          rc = certify_now(r);
-          if (rc) return rc;
-          if (cert_max <= 0.5 * tol) {
-            conv = true;
-            break;
-          }
-        }
-        if (iters % 50 == 0) residual(X, r);
-        launch_copy(r, n, z, n, n, nrhs, s);
-        msolve(z);
-        launch_col_dot(r, n, z, n, n, nrhs, rho_new, partial, s);
-        std::vector<double> h_rn(nrhs);
-        HIP_OK(hipMemcpyAsync(h_rn.data(), rho_new, nrhs * sizeof(double), hipMemcpyDeviceToHost,
-                              s));
-        HIP_OK(hipStreamSynchronize(s));
-        for (int64_t c = 0; c < nrhs; ++c) {
-          h_b[c] = (h_rho[c] != 0.0) ? h_rn[c] / h_rho[c] : 0.0;
-          h_rho[c] = h_rn[c];
-        }
-        HIP_OK(hipMemcpyAsync(beta, h_b.data(), nrhs * sizeof(double), hipMemcpyHostToDevice, s));
-        launch_axpby(z, n, pv, n, n, nrhs, nullptr, 1.0, beta, nullptr, s);  // p = z + beta p
-      }
-    }
+    R.run_pcg(max_iter, g_opt.pcg_recompute.load());
   }
-  HIP_OK(hipStreamSynchronize(s));
+  if (R.rc) return R.rc;
+  HIP_OK(hipStreamSynchronize(R.s));
+  bool conv = true;
+  double cert_max = 0.0;
+  for (int64_t c = 0; c < nrhs; ++c) {
+    conv = conv && R.passes(c);
+    cert_max = std::fmax(cert_max, R.cert[c]);
+  }
+  double res_max = 0.0;
+  for (int64_t c = 0; c < nrhs; ++c) res_max = std::fmax(res_max, std::sqrt(R.h_nrm[c]));
   if (rep) {
-    rep->iters = iters;
+    rep->iters = R.iters;
     rep->converged = conv ? 1 : 0;
     rep->cert = cert_max;
     rep->resid_norm = res_max;
+    rep->fallback_used = F->fallback | R.fallback;
     rep->time_ms =
         std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   }

@@ -45,12 +45,14 @@ void launch_max_diag(const double *A, int64_t lda, int64_t n, double *out, hipSt
 
 // Column-major FP64 A (lower) -> packed tiles, scaled by `scale`, identity
 // padding; only tile columns [c_begin, c_end) (c_end < 0: to the last).
+// diag_shift is added to the diagonal after scaling (the FP16 form's retry).
 void launch_pack(const double *A, int64_t n, int64_t lda, void *tiles, int store, int b,
                  int64_t N, double scale, hipStream_t s, int64_t c_begin = 0,
-                 int64_t c_end = -1);
-// Packed tiles -> dense column-major FP64 L (upper set to zero), times `scale`.
+                 int64_t c_end = -1, double diag_shift = 0.0);
+// Packed tiles -> dense column-major FP64 L (upper set to zero), times `scale`;
+// NaN everywhere in the lower triangle when *info != 0 (a failed factor).
 void launch_unpack(const void *tiles, int store, int b, int64_t N, int64_t n, double scale,
-                   double *L, int64_t ldl, hipStream_t s);
+                   double *L, int64_t ldl, const int64_t *info, hipStream_t s);
 
 // Step 1: factor diagonal tile c in place (FP64 arithmetic).  Sets *info.
 void launch_potrf(void *tiles, int store, int b, int64_t N, int64_t c, int64_t *info,
@@ -72,8 +74,9 @@ void launch_update(void *tiles, int store, int b, int64_t N, int64_t p0, int pw,
 // per workgroup, the default; 0: one tile per workgroup).  Same result.
 void set_f16_wide(int on);
 // FP16 copy of the finished panel columns [c0, c0 + pw) for tile rows
-// [c0, N), in the update kernel's layout: p16 holds N * 16 chunks of
-// 128 x 64 halves (panel width <= 16).
+// [c0, N), in the update kernel's layout: p16 holds N * 32 chunks of
+// 128 x 64 halves per panel buffer (two 64-column chunks per tile column of
+// the panel, panel width <= 16).
 constexpr int64_t kP16BytesPerTileRow = 32 * 128 * 64 * 2;
 void launch_panel_f16(const void *tiles, int64_t N, int64_t c0, int pw, void *p16,
                       const int64_t *info, hipStream_t s);
@@ -84,10 +87,11 @@ void launch_diag_inverse(const void *tiles, int store, int b, int64_t N, void *d
 // Forward then back substitution, in place on B (n x nrhs, ldb), FP64
 // arithmetic, one launch per direction (and per group of right-hand sides).
 // sync: device scratch of sync_words ints (>= 3), cleared by the launcher;
-// spin_max bounds each inter-workgroup wait (rows of an aborted solve are NaN).
+// spin_max bounds each inter-workgroup wait (rows of an aborted solve are NaN);
+// info: the factor's info word (every row is NaN when it is non-zero).
 void launch_solve(const void *tiles, const void *dinv, int store, int b, int64_t N, int64_t n,
                   double *B, int64_t ldb, int64_t nrhs, int *sync, int64_t sync_words,
-                  int spin_max, hipStream_t s);
+                  int spin_max, const int64_t *info, hipStream_t s);
 // Scale B by alpha in place (used by the scaled-FP16 factor).
 void launch_scale(double *B, int64_t n, int64_t ldb, int64_t nrhs, double alpha, hipStream_t s);
 
@@ -103,9 +107,18 @@ void launch_col_dot(const double *x, int64_t ldx, const double *y, int64_t ldy, 
 void launch_axpby(const double *x, int64_t ldx, double *y, int64_t ldy, int64_t n,
                   int64_t nrhs, const double *a, double a_sign, const double *bcoef,
                   const int32_t *active, hipStream_t s);
-// copy n x nrhs column-major blocks
+// copy n x nrhs column-major blocks (masked: only columns with mask[c] != 0)
 void launch_copy(const double *x, int64_t ldx, double *y, int64_t ldy, int64_t n,
                  int64_t nrhs, hipStream_t s);
+void launch_copy_masked(const double *x, int64_t ldx, double *y, int64_t ldy, int64_t n,
+                        int64_t nrhs, const int32_t *mask, hipStream_t s);
+// Preconditioned CG scalars per column: alpha = rho / (-pq) on active
+// columns (0 elsewhere, or for a zero / non-finite denominator); beta =
+// rho_new / rho and rho <- rho_new on active columns (beta 0 elsewhere).
+void launch_pcg_alpha(const double *rho, const double *pq, const int32_t *act, double *alpha,
+                      int64_t nrhs, hipStream_t s);
+void launch_pcg_beta(const double *rho_new, double *rho, const int32_t *act, double *beta,
+                     int64_t nrhs, hipStream_t s);
 
 // Kernel timing hooks (option "profile"): profile_begin records an event
 // on s before a launch, profile_end one after it and files the pair with the

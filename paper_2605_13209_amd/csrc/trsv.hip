@@ -17,7 +17,10 @@
 // hardware dispatches first, so the chain always progresses; as a safety net
 // the wait is bounded: after spin_max polls the waiter raises the abort word,
 // every other waiter then stops waiting, and the aborted block rows are
-// written as NaN (never a hang, never a silently wrong number).
+// written as NaN (never a hang, never a silently wrong number).  The same
+// NaN output is written when the factorisation's info word is non-zero (a
+// failed factor whose failure the host has not read yet): the chain still
+// runs, so every workgroup publishes and exits as usual.
 //
 // Each tile a workgroup applies is loaded straight into registers before the
 // wait (its memory latency hides behind the wait), 512 threads.  With 16
@@ -90,7 +93,8 @@ __global__ __launch_bounds__(NT) void solve_kernel(const T *__restrict__ tiles,
                                                    const T *__restrict__ dinv, int64_t N,
                                                    int64_t n, double *__restrict__ X, int64_t ldx,
                                                    int64_t nrhs, int *__restrict__ counters,
-                                                   int *__restrict__ abort_word, int spin_max) {
+                                                   int *__restrict__ abort_word, int spin_max,
+                                                   const int64_t *__restrict__ info) {
   constexpr int G = NT / B, CPG = B / G;
   __shared__ SolveSmem<B, KR> sm;
   __shared__ int ok_sh;
@@ -150,7 +154,7 @@ __global__ __launch_bounds__(NT) void solve_kernel(const T *__restrict__ tiles,
   };
 
   int seen = 0;
-  bool good = true;
+  bool good = *info == 0;
   // this block row's own right-hand side (forward b_i, back y_i), loaded up
   // front so that its latency is off the critical path
   for (int e = t; e < B * KR; e += NT) {
@@ -317,7 +321,8 @@ __global__ void scale_kernel(double *B_, int64_t n, int64_t ldb, int64_t nrhs, d
 
 template <int B, int KR, typename T>
 void solve_run(const T *tiles, const T *dinv, int64_t N, int64_t n, double *X, int64_t ldx,
-               int64_t nrhs, int *sync, int64_t sync_words, int spin_max, hipStream_t s) {
+               int64_t nrhs, int *sync, int64_t sync_words, int spin_max, const int64_t *info,
+               hipStream_t s) {
   // sync = [abort, forward counters (nch), back counters (nch)]
   const int64_t max_ch = (sync_words - 1) / 2;
   for (int64_t c0 = 0; c0 < nrhs; c0 += max_ch * KR) {
@@ -327,43 +332,44 @@ void solve_run(const T *tiles, const T *dinv, int64_t N, int64_t n, double *X, i
     const dim3 grid((unsigned)N, (unsigned)nch);
     double *Xc = X + c0 * ldx;
     hipLaunchKernelGGL((solve_kernel<B, KR, true, T>), grid, dim3(NT), 0, s, tiles, dinv, N, n,
-                       Xc, ldx, k, sync + 1, sync, spin_max);
+                       Xc, ldx, k, sync + 1, sync, spin_max, info);
     hipLaunchKernelGGL((solve_kernel<B, KR, false, T>), grid, dim3(NT), 0, s, tiles, dinv, N, n,
-                       Xc, ldx, k, sync + 1 + nch, sync, spin_max);
+                       Xc, ldx, k, sync + 1 + nch, sync, spin_max, info);
   }
 }
 
 template <int B, typename T>
 void solve_rhs(const T *tiles, const T *dinv, int64_t N, int64_t n, double *X, int64_t ldx,
-               int64_t nrhs, int *sync, int64_t sync_words, int spin_max, hipStream_t s) {
+               int64_t nrhs, int *sync, int64_t sync_words, int spin_max, const int64_t *info,
+               hipStream_t s) {
   if (nrhs == 1)
-    solve_run<B, 1, T>(tiles, dinv, N, n, X, ldx, nrhs, sync, sync_words, spin_max, s);
+    solve_run<B, 1, T>(tiles, dinv, N, n, X, ldx, nrhs, sync, sync_words, spin_max, info, s);
   else if (nrhs <= 4)
-    solve_run<B, 4, T>(tiles, dinv, N, n, X, ldx, nrhs, sync, sync_words, spin_max, s);
+    solve_run<B, 4, T>(tiles, dinv, N, n, X, ldx, nrhs, sync, sync_words, spin_max, info, s);
   else
-    solve_run<B, 16, T>(tiles, dinv, N, n, X, ldx, nrhs, sync, sync_words, spin_max, s);
+    solve_run<B, 16, T>(tiles, dinv, N, n, X, ldx, nrhs, sync, sync_words, spin_max, info, s);
 }
 
 }  // namespace
 
 void launch_solve(const void *tiles, const void *dinv, int store, int b, int64_t N, int64_t n,
                   double *X, int64_t ldx, int64_t nrhs, int *sync, int64_t sync_words,
-                  int spin_max, hipStream_t s) {
+                  int spin_max, const int64_t *info, hipStream_t s) {
   if (N <= 0 || nrhs <= 0 || sync_words < 3) return;
   if (b == 128) {
     if (store == STORE_F64)
       solve_rhs<128, double>((const double *)tiles, (const double *)dinv, N, n, X, ldx, nrhs,
-                             sync, sync_words, spin_max, s);
+                             sync, sync_words, spin_max, info, s);
     else
       solve_rhs<128, float>((const float *)tiles, (const float *)dinv, N, n, X, ldx, nrhs, sync,
-                            sync_words, spin_max, s);
+                            sync_words, spin_max, info, s);
   } else {
     if (store == STORE_F64)
       solve_rhs<64, double>((const double *)tiles, (const double *)dinv, N, n, X, ldx, nrhs,
-                            sync, sync_words, spin_max, s);
+                            sync, sync_words, spin_max, info, s);
     else
       solve_rhs<64, float>((const float *)tiles, (const float *)dinv, N, n, X, ldx, nrhs, sync,
-                           sync_words, spin_max, s);
+                           sync_words, spin_max, info, s);
   }
 }
 

@@ -35,14 +35,15 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_factor_bytes():
-    # packed lower tiles N(N+1)/2, N transposed diagonal blocks, 256-byte header
-    assert P.chol_factor_bytes(1024, "fp64", 128) == 256 + (36 + 8) * 128 * 128 * 8
-    assert P.chol_factor_bytes(1000, "fp32", 128) == 256 + (36 + 8) * 128 * 128 * 4
-    assert P.chol_factor_bytes(65536, "fp64", 128) == 256 + (512 * 513 // 2 + 512) * 128 * 128 * 8
+    # packed lower tiles N(N+1)/2, N transposed diagonal blocks, 512-byte header
+    # (info word, scaling, the solves' synchronisation words)
+    assert P.chol_factor_bytes(1024, "fp64", 128) == 512 + (36 + 8) * 128 * 128 * 8
+    assert P.chol_factor_bytes(1000, "fp32", 128) == 512 + (36 + 8) * 128 * 128 * 4
+    assert P.chol_factor_bytes(65536, "fp64", 128) == 512 + (512 * 513 // 2 + 512) * 128 * 128 * 8
     # FP16 form: FP32 tiles plus two FP16 panel buffers of N * 32 chunks of 128 x 64 halves
     assert P.chol_factor_bytes(1024, "fp16_scaled", 128) == \
-        256 + (36 + 8) * 128 * 128 * 4 + 2 * 8 * 32 * 128 * 64 * 2
-    assert P.chol_factor_bytes(0, "fp64", 64) == 256
+        512 + (36 + 8) * 128 * 128 * 4 + 2 * 8 * 32 * 128 * 64 * 2
+    assert P.chol_factor_bytes(0, "fp64", 64) == 512
     assert P.chol_factor_bytes(10, "fp64", 96) == 0
     assert P.chol_factor_bytes(-1, "fp64", 64) == 0
     assert P.chol_tile_default(200) == 64 and P.chol_tile_default(4096) == 128
@@ -82,7 +83,10 @@ def test_argument_validation_without_device():
     assert lib.gp_assemble(ctypes.c_void_p(256), 10, 8, 8, 0.0, 1.0, 0.1, ctypes.c_void_p(256), 10, 1, None) == -5
     assert lib.gp_assemble(ctypes.c_void_p(256), 10, 8, 8, 1.0, 1.0, 0.1, ctypes.c_void_p(256), 9, 1, None) == -9
     assert lib.chol_solve(None, None, 1, 1, None) == -105
-    assert lib.chol_refine_bytes(100, 2, 0) == 2 * 100 * 2 * 8 + (8 + 128) * 2 * 8 + 256
+    # five n x nrhs blocks, 138 doubles per right-hand side, 256 bytes; both methods
+    assert lib.chol_refine_bytes(100, 2, 0) == 5 * 100 * 2 * 8 + 138 * 2 * 8 + 256
+    assert lib.chol_refine_bytes(100, 2, 1) == lib.chol_refine_bytes(100, 2, 0)
+    assert lib.chol_refine_bytes(100, 2, 7) == 0
 
 
 def test_product_path_fails_loudly_without_library(monkeypatch):

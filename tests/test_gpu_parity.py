@@ -336,6 +336,52 @@ def test_full_size_sampled_parity():
     assert oracle.certificate(r, x, hp[2]) <= 1e-10
 
 
+def test_full_size_fp64_n65536():
+    """The headline FP64 configuration (n = 65536, tile 128, automatic
+    schedule), the first FP64 order whose packed element offsets pass 2^31:
+    sampled entries of L L^T against the oracle's A_ij within the
+    componentwise bound, the randomized backward error of the whole factor
+    (A matrix-free from the features, long double) <= 1e-12, and the k = 1
+    solve certified to 1e-10 by the oracle's matrix-free residual."""
+    torch.cuda.empty_cache()
+    n = 65536
+    X, B = gp_inputs.gp_problem(n, seed=0, k=1)
+    hp = (1.0, 1.0, 0.1)
+    Ad = P.gp_assemble(torch.from_numpy(X).cuda(), *hp, full=False)
+    F = P.chol_factor(Ad, "fp64", 128)
+    assert F.info() == 0
+    del Ad
+    torch.cuda.empty_cache()
+    Ld = P.chol_factor_to_dense(F)
+    rng = np.random.default_rng(17)
+    pairs = [(int(i), int(rng.integers(0, i + 1))) for i in rng.integers(0, n, size=48)]
+    # entries whose packed offsets lie past 2^31 elements, the last tile, a tile edge
+    pairs += [(n - 1, n - 1), (n - 1, 0), (n - 1, n - 200), (60000, 59000), (50000, 30000), (255, 128)]
+    rows = sorted({r for pr in pairs for r in pr})
+    Lrows = {r: host(Ld[r, :]).astype(np.float64) for r in rows}
+    gam = (n + 1) * U / (1 - (n + 1) * U)
+    for i, j in pairs:
+        li, lj = Lrows[i][: j + 1], Lrows[j][: j + 1]
+        s = float(np.sum(li.astype(np.longdouble) * lj.astype(np.longdouble)))
+        a = oracle.gp_entry(X, i, j, *hp)
+        bound = gam * float(np.sum(np.abs(li) * np.abs(lj))) + 8 * U * abs(a)
+        assert abs(s - a) <= bound, (i, j, s, a, bound)
+    Lh = host(Ld)
+    del Ld
+    torch.cuda.empty_cache()
+    Z = np.random.default_rng(19).standard_normal((n, 2))
+    est, _, _ = oracle.backward_error_estimate(Lh, Z, Xfeat=X, lengthscale=hp[0], variance=hp[1], noise=hp[2])
+    del Lh
+    assert est <= 1e-12, est
+    Bd = dev(B)
+    P.chol_solve(F, Bd)
+    x = host(Bd)[:, 0]
+    r = oracle.gp_residual(X, *hp, x, B[:, 0])
+    assert oracle.certificate(r, x, hp[2]) <= 1e-10
+    del F
+    torch.cuda.empty_cache()
+
+
 def test_full_size_mixed_fp32_n65536():
     """The mixed-precision bench configuration (n = 65536, SE lengthscale 1,
     noise 0.1, one right-hand side, FP32 factor, FP64 A for the residuals):

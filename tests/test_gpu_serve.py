@@ -56,6 +56,30 @@ def test_alone_equals_mix_bitwise():
         assert a.iters == m.iters
 
 
+def test_serving_large_sample_matches_oracle_and_mix():
+    """The serving configuration's upper range (n up to 8192, up to 64
+    right-hand sides): each result matches the oracle's refined solution, and
+    is bitwise the same alone and in a concurrent mix."""
+    reqs = make_requests(seed=3, sizes=(8192, 5000, 2900, 6144, 1500), kmax=64)
+    reqs[0].B = gp_inputs.gp_problem(8192, d=8, k=64, seed=200)[1]  # the largest corner: n = 8192, k = 64
+    ex = HipExecutor(workers=4)
+    with Server(ex, hbm_budget=16e9, max_inflight=1, cache=False) as s:
+        alone = [s.submit(clone(r)).result(timeout=300) for r in reqs]
+    with Server(ex, hbm_budget=16e9, max_inflight=4, cache=False) as s:
+        futs = [s.submit(clone(r)) for r in reqs]
+        mixed = [f.result(timeout=300) for f in futs]
+    for r, a, m in zip(reqs, alone, mixed):
+        assert np.array_equal(a.X, m.X) and a.iters == m.iters
+        assert a.converged and a.cert <= 0.5e-10
+        A = oracle.gp_assemble(r.X, r.lengthscale, r.variance, r.noise)
+        L, info = oracle.cholesky(A)
+        assert info == 0
+        xref, _, _, failed = oracle.refine(L, A, r.B, lam=r.noise, tol=1e-13)
+        assert failed == 0
+        err = np.linalg.norm(a.X - xref, axis=0) / np.linalg.norm(xref, axis=0)
+        assert err.max() <= 1e-10, (r.n, r.k, err.max())
+
+
 def test_factor_reuse():
     r = make_requests(seed=2, sizes=(800,))[0]
     with Server(HipExecutor(workers=2), hbm_budget=8e9, max_inflight=2) as s:
