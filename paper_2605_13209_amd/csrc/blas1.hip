@@ -9,6 +9,7 @@ namespace chol {
 namespace {
 
 __device__ inline void two_sum(double a, double b, double &s, double &e) {
+#pragma clang fp contract(off)
   s = a + b;
   const double bb = s - a;
   e = (a - (s - bb)) + (b - bb);
@@ -25,12 +26,15 @@ __device__ inline void two_sum(double a, double b, double &s, double &e) {
 // quarter of the block's columns in double-double (TwoProd by fma, TwoSum),
 // with two independent accumulators per right-hand side for instruction-level
 // parallelism, so the residual's own rounding is far below FP64 round-off of
-// |A||x| even at n ~ 1e5.  Every reduction has a fixed order.
+// |A||x| even at n ~ 1e5.  Every reduction has a fixed order.  Contraction is
+// off in the kernel: a product fused into the following TwoSum (hs + av * xv
+// as one fma) would make the error terms count the product's rounding twice.
 template <int NR>
 __global__ __launch_bounds__(256) void symm_residual_kernel(
     const double *__restrict__ A, int64_t lda, int64_t n, const double *__restrict__ X,
     int64_t ldx, const double *__restrict__ Bm, int64_t ldb, double *__restrict__ R, int64_t ldr,
     int64_t nrhs) {
+#pragma clang fp contract(off)
   constexpr int P = 65;
   constexpr int NA = 2;  // accumulators per right-hand side
   __shared__ double at[2][64 * P];  // at[.][jj * P + ii] = A(I0 + ii, J0 + jj)

@@ -236,3 +236,26 @@ def test_solves_on_two_streams_share_a_factor():
     for _, Bd in outs:
         x = host(Bd)
         assert np.linalg.norm(x - xref) / np.linalg.norm(xref) <= 1e-10
+
+
+def test_residual_is_double_double_accurate():
+    """R = B - A X near a solution (|R| about 14 digits below |A||X|): the
+    stored-matrix residual kernel accumulates in double-double, so each entry
+    is within a few ulp of itself against the exact (rational) residual, not
+    merely within u |A||X|."""
+    from fractions import Fraction
+    n, hp = 200, (0.7, 1.0, 0.05)
+    X, B = gp_inputs.gp_problem(n, seed=41, k=2)
+    A = oracle.gp_assemble(X, *hp)
+    xs = np.asfortranarray(np.linalg.solve(A, B))
+    U = np.finfo(np.float64).eps / 2
+    R = host(P.chol_residual(dev(A), dev(xs), dev(B)))
+    for c in range(2):
+        xf = [Fraction(float(v)) for v in xs[:, c]]
+        for i in range(n):
+            s = Fraction(float(B[i, c]))
+            for j in range(n):
+                s -= Fraction(float(A[i, j])) * xf[j]
+            ex = float(s)
+            absAx = float(np.abs(A[i]) @ np.abs(xs[:, c]))
+            assert abs(R[i, c] - ex) <= 2 * U * abs(ex) + 64 * n * U * U * absAx, (i, c, R[i, c], ex)
