@@ -262,6 +262,34 @@ int chol_refine_solve(chol_handle F, const double *A, int64_t lda,
                       void *workspace, size_t ws_bytes,
                       chol_refine_report *rep, void *stream);
 
+/* ---- chol_refine_solve_noalloc ------------------------------------------
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * chol_refine_solve with the same arguments and results, minus the
+ * workspace, which is replaced by a static device array of
+ * chol_refine_noalloc_max_bytes() bytes (64 MiB) inside the library, held by
+ * every GPU the library runs on until the process ends.  The call allocates
+ * no device memory (no hipMalloc / hipFree, no allocating library routine).
+ * It serves n x nrhs problems with chol_refine_bytes(n, nrhs, method) up to
+ * that size (n * nrhs up to about 1.6 million, e.g. n = 8192 with 64
+ * right-hand sides, n = 65536 with 16); larger problems return
+ * CHOL_ERR_WORKSPACE before any device work.
+ * Every call on one GPU shares that GPU's array: calls that overlap in time
+ * on one GPU (from several host threads or streams) race and give wrong
+ * results; serialise them.  The array keeps the last call's contents; each
+ * call writes every part of it before reading it.
+ * Errors: those of chol_refine_solve, CHOL_ERR_WORKSPACE for a problem too
+ * large for the array, CHOL_ERR_HIP if the array's device address cannot be
+ * found (looked up once per device, on the first call on it).            */
+size_t chol_refine_noalloc_max_bytes(void);
+int chol_refine_solve_noalloc(chol_handle F, const double *A, int64_t lda,
+                              const double *Xf, int64_t d, int64_t ldxf,
+                              double lengthscale, double variance, double noise,
+                              const double *B, int64_t ldb, double *X,
+                              int64_t ldxs, int64_t nrhs, double tol,
+                              int max_iter, int method,
+                              chol_refine_report *rep, void *stream);
+
 /* ---- chol_residual -----------------------------------------------------
  * R = B - A X in FP64 with A symmetric given by its lower triangle (lda),
  * all n x nrhs column-major device arrays.  Deterministic (no atomics).   */

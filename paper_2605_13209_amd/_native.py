@@ -64,6 +64,9 @@ EXPORTS = {
     "chol_refine_solve": (_int, [_vp, _vp, _i64, _vp, _i64, _i64, _dbl, _dbl, _dbl, _vp, _i64, _vp,
                                  _i64, _i64, _dbl, _int, _int, _vp, _sz, ctypes.POINTER(RefineReport),
                                  _vp]),
+    "chol_refine_noalloc_max_bytes": (_sz, []),
+    "chol_refine_solve_noalloc": (_int, [_vp, _vp, _i64, _vp, _i64, _i64, _dbl, _dbl, _dbl, _vp, _i64, _vp,
+                                         _i64, _i64, _dbl, _int, _int, ctypes.POINTER(RefineReport), _vp]),
     "chol_residual": (_int, [_vp, _i64, _i64, _vp, _i64, _vp, _i64, _vp, _i64, _i64, _vp]),
     "chol_factor_to_dense": (_int, [_vp, _vp, _i64, _vp]),
     "chol_factor_n": (_i64, [_vp]),
@@ -302,6 +305,37 @@ def chol_refine_solve(F: Factor, B: torch.Tensor, *, A: torch.Tensor | None = No
         _check(rc, "chol_refine_solve")
     return RefineResult(X, rep.iters, bool(rep.converged), rep.cert, rep.resid_norm, rep.time_ms, rc,
                         rep.fallback_used)
+
+
+def chol_refine_solve_noalloc(F: Factor, B: torch.Tensor, out: torch.Tensor, *, A: torch.Tensor | None = None,
+                              X_feat: torch.Tensor | None = None, lengthscale: float = 1.0,
+                              variance: float = 1.0, noise: float = 0.0, tol: float = 1e-10, max_iter: int = 30,
+                              method: str | int = "ir", raise_on_fail: bool = True, stream=None) -> RefineResult:
+    """chol_refine_solve with the library's static device scratch array instead
+    of a workspace (no device allocation by the library; ``out`` is required,
+    so the binding allocates nothing either)."""
+    _need_device(B, "B")
+    _need_device(out, "out")
+    n, k = B.shape
+    m = int(METHODS.get(method, method))
+    rep = RefineReport()
+    a_ptr, lda = (A.data_ptr(), _ld(A)) if A is not None else (None, max(1, n))
+    if X_feat is not None:
+        xf_ptr, d, ldxf = X_feat.data_ptr(), X_feat.shape[1], max(X_feat.shape[1], X_feat.stride(0))
+    else:
+        xf_ptr, d, ldxf = None, 0, 0
+    rc = lib().chol_refine_solve_noalloc(F.handle, a_ptr, lda, xf_ptr, d, ldxf, float(lengthscale),
+                                         float(variance), float(noise), B.data_ptr(), _ld(B), out.data_ptr(),
+                                         _ld(out), k, float(tol), int(max_iter), m, ctypes.byref(rep),
+                                         _stream(stream))
+    if rc not in (0, CHOL_ERR_NOT_CONVERGED) or (rc != 0 and raise_on_fail):
+        _check(rc, "chol_refine_solve_noalloc")
+    return RefineResult(out, rep.iters, bool(rep.converged), rep.cert, rep.resid_norm, rep.time_ms, rc,
+                        rep.fallback_used)
+
+
+def chol_refine_noalloc_max_bytes() -> int:
+    return int(lib().chol_refine_noalloc_max_bytes())
 
 
 def chol_residual(A: torch.Tensor, X: torch.Tensor, B: torch.Tensor, out: torch.Tensor | None = None,

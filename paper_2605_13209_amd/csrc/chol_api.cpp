@@ -506,6 +506,11 @@ int chol_factor_ex(const double *A, int64_t n, int64_t lda, int precision,
   (void)hipGetDevice(&F->device);
   F->d_info = (int64_t *)workspace;
   F->sync = (int *)((char *)workspace + kSolveSyncOff);
+  if (hipEventCreateWithFlags(&F->ev_solve, hipEventDisableTiming) != hipSuccess) {
+    F->ev_solve = nullptr;
+    delete F;
+    return CHOL_ERR_HIP;
+  }
   F->tiles = (char *)workspace + kHeader;
   F->dinv = (char *)F->tiles + (size_t)tile_count(F->N) * (size_t)tile * tile * esize_of(precision);
   if (precision == CHOL_FP16_SCALED)
@@ -693,7 +698,6 @@ int chol_solve(chol_handle F, double *B, int64_t nrhs, int64_t ldb, void *stream
   launch_solve(F->tiles, F->dinv, st, F->b, F->N, F->n, B, ldb, nrhs, F->sync, kSolveSyncWords,
                (int)g_opt.solve_spin_max.load(), F->d_info, s);
   if (F->scale != 1.0) launch_scale(B, F->n, ldb, nrhs, 1.0 / F->scale, s);
-  if (!F->ev_solve) HIP_OK(hipEventCreateWithFlags(&F->ev_solve, hipEventDisableTiming));
   HIP_OK(hipEventRecord(F->ev_solve, s));
   F->last_solve = s;
   F->solved = true;
@@ -1037,6 +1041,58 @@ int chol_refine_solve(chol_handle F, const double *A, int64_t lda, const double 
         std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   }
   return conv ? CHOL_OK : CHOL_ERR_NOT_CONVERGED;
+}
+
+// ------------------------------------------- refinement without allocation ----
+// A file-scope device array replaces the caller's workspace.  In host code
+// `scratch` names a host-side stand-in, not device memory: its device address
+// is looked up once per device with hipGetSymbolAddress (on the first call
+// on that device, with the device current) and only that address is passed
+// to the kernels.  Every buffer in it is written before it is read, so
+// nothing needs clearing between calls.
+}  // extern "C"
+
+namespace {
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+std::mutex g_scratch_mu;
+std::vector<std::pair<int, void *>> g_scratch;  // (device, device address of scratch)
+
+int scratch_address(void **out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return CHOL_ERR_HIP;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  for (const auto &e : g_scratch)
+    if (e.first == dev) {
+      *out = e.second;
+      return CHOL_OK;
+    }
+  void *p = nullptr;
+  if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return CHOL_ERR_HIP;
+  g_scratch.emplace_back(dev, p);
+  *out = p;
+  return CHOL_OK;
+}
+}  // namespace
+
+extern "C" {
+
+size_t chol_refine_noalloc_max_bytes(void) { return kScratchBytes; }
+
+int chol_refine_solve_noalloc(chol_handle F, const double *A, int64_t lda, const double *Xf,
+                              int64_t d, int64_t ldxf, double lengthscale, double variance,
+                              double noise, const double *B, int64_t ldb, double *X,
+                              int64_t ldxs, int64_t nrhs, double tol, int max_iter, int method,
+                              chol_refine_report *rep, void *stream) {
+  if (!F) return CHOL_ERR_BAD_HANDLE;
+  if (nrhs < 0) return -14;
+  if (method != CHOL_REFINE_IR && method != CHOL_REFINE_PCG) return -17;
+  if (chol_refine_bytes(F->n, nrhs, method) > kScratchBytes) return CHOL_ERR_WORKSPACE;
+  void *ws = nullptr;
+  const int rc = scratch_address(&ws);
+  if (rc) return rc;
+  return chol_refine_solve(F, A, lda, Xf, d, ldxf, lengthscale, variance, noise, B, ldb, X, ldxs,
+                           nrhs, tol, max_iter, method, ws, kScratchBytes, rep, stream);
 }
 
 }  // extern "C"
