@@ -46,31 +46,28 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# Bytes moved between L2 and the memory fabric per launch of the bulk FP64
-# update (update_f64_kernel<0>) in the n = 32768 workload (panel width 8, 30
-# launches per factorisation): two rocprofv3 --pmc runs (FETCH_SIZE,
-# WRITE_SIZE) over one factorisation, each scaled by what the same counter
-# reads for a plain 1 GiB copy (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0).  Valid
-# only for the kernel source it was measured on; otherwise reported as null.
-# Algorithmic bytes per launch (each C tile read and written once, each panel
-# tile read once): 2.790e9.
-TRAFFIC = {"update_hip_sha256_16": "997d8b127706b215", "n": 32768, "bytes_per_launch": 7.902e9,
-           "algorithmic_bytes_per_launch": 2.790e9,
-           "source": "profiles/update_f64_kernel_traffic_n32768.md"}
-
-# The same for the whole-triangle update of the mixed forms: FP32
-# (update_f32_kernel<0>, n = 65536, 124 launches) and FP16-scaled
-# (update_f16_wide_kernel, n = 131072, 62 launches).  Their algorithmic bytes
-# are estimates from the panel schedule (trailing region of N - (p + 2) w tile
-# rows after panel p; C tiles in FP32 read and written once, panel tiles read
-# once in FP32 or FP16).
-F32_TRAFFIC = {"update_hip_sha256_16": "997d8b127706b215", "n": 65536, "bytes_per_launch": 1.951e10,
-               "algorithmic_bytes_per_launch": 5.79e9,
-               "source": "profiles/update_f32_kernel_traffic_n65536.md"}
-F16_TRAFFIC = {"update_hip_sha256_16": "997d8b127706b215", "n": 131072, "bytes_per_launch": 5.094e10,
-               "algorithmic_bytes_per_launch": 2.23e10,
-               "source": "profiles/update_f16_wide_kernel_traffic_n131072.md"}
-TRAFFIC_BY_DTYPE = {"f64": TRAFFIC, "f32": F32_TRAFFIC, "f16": F16_TRAFFIC}
+# Bytes moved between L2 and the memory fabric per launch of the bulk
+# (whole-trailing-triangle) update, from two rocprofv3 --pmc runs (FETCH_SIZE,
+# WRITE_SIZE) over one run of the workload, each scaled by what the same
+# counter reads for a plain 1 GiB copy (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0).
+# Keyed by (operand precision, n); valid only for the kernel source they were
+# measured on, otherwise reported as null.  Algorithmic bytes per launch: each
+# C tile read and written once, each panel tile read once, averaged over the
+# launches of one factorisation (panel width 8; width 16 for FP16).
+TRAFFIC_RECORDS = {
+    ("f64", 65536): {"update_hip_sha256_16": "997d8b127706b215", "bytes_per_launch": 3.275e10,
+                     "algorithmic_bytes_per_launch": 1.131e10,
+                     "source": "profiles/update_f64_kernel_traffic_n65536.md"},
+    ("f64", 32768): {"update_hip_sha256_16": "997d8b127706b215", "bytes_per_launch": 7.902e9,
+                     "algorithmic_bytes_per_launch": 2.790e9,
+                     "source": "profiles/update_f64_kernel_traffic_n32768.md"},
+    ("f32", 65536): {"update_hip_sha256_16": "997d8b127706b215", "bytes_per_launch": 1.926e10,
+                     "algorithmic_bytes_per_launch": 5.65e9,
+                     "source": "profiles/update_f32_kernel_traffic_n65536.md"},
+    ("f16", 131072): {"update_hip_sha256_16": "997d8b127706b215", "bytes_per_launch": 5.094e10,
+                      "algorithmic_bytes_per_launch": 2.23e10,
+                      "source": "profiles/update_f16_wide_kernel_traffic_n131072.md"},
+}
 
 # The same for the CG tile product (symv_tiles_kernel<128>) at n = 65536:
 # FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 per launch.
@@ -131,7 +128,7 @@ def _update_roofline(kms, kl, kfl, peak, dtype, n, kernel):
     return {"bound": "mfma", "achieved": round(ach, 3), "peak": peak, "unit": "TFLOP/s",
             "frac": round(ach / peak, 4), "traffic": tr,
             "traffic_unit": "bytes per launch between L2 and the memory fabric (calibrated counters)",
-            "algorithmic_bytes_per_launch": TRAFFIC_BY_DTYPE[dtype]["algorithmic_bytes_per_launch"] if tr else None,
+            "algorithmic_bytes_per_launch": TRAFFIC_RECORDS[(dtype, n)]["algorithmic_bytes_per_launch"] if tr else None,
             "kernel": kernel, "launches": kl, "avg_launch_us": round(kms * 1e3 / kl, 2),
             "avg_launch_gflop": round(kfl / kl / 1e9, 4)}
 
@@ -679,7 +676,7 @@ def bench_fp16(args):
                     "unit": "TFLOP/s", "frac": round(ach / FP16_PEAK_TFLOPS, 4),
                     "traffic": measured_traffic(n, "f16"),
                     "traffic_unit": "bytes per launch between L2 and the memory fabric (calibrated counters)",
-                    "algorithmic_bytes_per_launch": F16_TRAFFIC["algorithmic_bytes_per_launch"]
+                    "algorithmic_bytes_per_launch": TRAFFIC_RECORDS[("f16", n)]["algorithmic_bytes_per_launch"]
                     if measured_traffic(n, "f16") else None,
                     "kernel": "update_f16_wide_kernel (Step-3 update of the trailing triangle, 2 x 2 tiles per workgroup)",
                     "launches": kl, "avg_launch_us": round(kms * 1e3 / kl, 2),
@@ -708,10 +705,10 @@ def bench_fp16(args):
 
 def measured_traffic(n: int, dtype: str):
     """Counter-measured bytes per launch of the bulk update (dtype f64, f32 or
-    f16: the update's operand precision), or None when the workload or the
-    kernel source differs from the one the counters saw."""
+    f16: the update's operand precision), or None when no record covers this
+    order or the kernel source differs from the one the counters saw."""
     import hashlib
-    rec = TRAFFIC_BY_DTYPE.get(dtype)
+    rec = TRAFFIC_RECORDS.get((dtype, n))
     if rec is None:
         return None
     src = os.path.join(ROOT, "paper_2605_13209_amd", "csrc", "update.hip")
@@ -719,7 +716,7 @@ def measured_traffic(n: int, dtype: str):
         h = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
     except OSError:
         return None
-    if n != rec["n"] or h != rec["update_hip_sha256_16"]:
+    if h != rec["update_hip_sha256_16"]:
         return None
     return rec["bytes_per_launch"]
 
