@@ -254,7 +254,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="headline_n65536",
                     choices=["headline_n65536", "fp64_n32768", "fp64_n1024", "fp64_n65536", "mixed_n65536",
-                             "mixed_fp16_n131072", "serve", "cg_n65536"])
+                             "mixed_fp16_n131072", "serve", "cg_n65536", "hetero"])
+    ap.add_argument("--shares", default="1.0,0.999,0.997,0.995,0.99,0.98,0.95,0.9",
+                    help="hetero: GPU shares of the Step-3 tiles to sweep")
     ap.add_argument("--no-sub", action="store_true",
                     help="headline: skip the other configurations' summaries (n = 1024, 32768, 131072, serving)")
     ap.add_argument("--duration", type=float, default=30.0, help="serve: seconds of arrivals")
@@ -310,6 +312,8 @@ def main():
         out = bench_fp16(args)
     elif wl == "cg_n65536":
         out = bench_cg(args)
+    elif wl == "hetero":
+        out = bench_hetero(args)
     elif wl == "headline_n65536":
         out = bench_headline(args)
         if not args.no_cpu_baseline:
@@ -500,6 +504,74 @@ def bench_chol(args):
            "vs_baseline": None, "dtype": dtype, "data": "synthetic", "config": config,
            "roofline": roofline}
     out.update(extra)
+    return out
+
+
+def bench_hetero(args):
+    """The paper's heterogeneous CPU + GPU Cholesky against the GPU alone:
+    SE kernel d=8, lengthscale 1, variance 1, noise 0.1, seed 0, FP64, tile
+    128, A resident in HBM.  For each GPU share of the Step-3 tiles in
+    --shares, chol_factor_hetero is timed (wall time of the synchronous call,
+    host <-> device copies of the CPU's rows included); the GPU-alone line is
+    chol_factor with its tuned schedule (panel width 8, lookahead).  value =
+    n^3/3 over the best heterogeneous time."""
+    import torch
+    import gp_inputs
+    import paper_2605_13209_amd as P
+    n = args.n or 32768
+    steps = args.steps if args.steps != 10 else 2
+    X_np, B_np = gp_inputs.gp_problem(n, d=8, k=1, seed=0)
+    Xd = torch.from_numpy(X_np).cuda()
+    Bd = P.to_colmajor(torch.from_numpy(B_np))
+    A = P.colmajor_empty(n, n)
+    P.gp_assemble(Xd, *HP, full=False, out=A)
+    ws = torch.empty(P.chol_factor_bytes(n, "fp64", 128), dtype=torch.uint8, device="cuda")
+    host_ws = torch.empty(P.chol_hetero_host_bytes(n), dtype=torch.uint8, pin_memory=True)
+    flops = n ** 3 / 3
+
+    def timed(fn):
+        ts = []
+        for r in range(1 + steps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            res = fn()
+            torch.cuda.synchronize()
+            if r >= 1:
+                ts.append((time.perf_counter() - t0) * 1e3)
+        return float(np.mean(ts)), res
+
+    t_gpu, F = timed(lambda: P.chol_factor(A, "fp64", 128, workspace=ws))
+    curve = []
+    for share in [float(v) for v in args.shares.split(",")]:
+        t, (F, rep) = timed(lambda: P.chol_factor_hetero(A, share, workspace=ws, host_ws=host_ws))
+        b = P.colmajor_empty(n, 1)
+        b.copy_(Bd)
+        P.chol_solve(F, b)
+        R = P.chol_residual(A, b, Bd)
+        cert = float(torch.linalg.norm(R) / (HP[2] * torch.linalg.norm(b)))
+        curve.append({"gpu_share": share, "ms": round(t, 2), "gflops": round(flops / (t * 1e-3) / 1e9, 1),
+                      "gpu_share_tiles": round(rep["gpu_share_tiles"], 5),
+                      "border_shifts": rep["border_shifts"], "handover_column": rep["handover_column"],
+                      "ms_cpu": round(rep["ms_cpu"], 1), "ms_wait_gpu": round(rep["ms_wait_gpu"], 1),
+                      "gb_h2d": round(rep["bytes_h2d"] / 1e9, 3), "gb_d2h": round(rep["bytes_d2h"] / 1e9, 3),
+                      "cpu_threads": rep["cpu_threads"], "solve_cert": cert})
+        print(f"bench: hetero n={n} share={share} {t:.1f} ms", file=sys.stderr, flush=True)
+    best = min(curve, key=lambda c: c["ms"])
+    out = {"metric": METRIC, "value": best["gflops"], "unit": "GFLOP/s", "n_gpus": 1, "steps": steps,
+           "warmup": 1, "ms_per_step": best["ms"], "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": f"hetero_cpu_gpu_cholesky_n{n}", "n": n, "tile": 128, "panel_width": 8,
+                      "kernel": "SE d=8 lengthscale=1 variance=1 noise=0.1", "seed": 0,
+                      "value_is": "n^3/3 / best heterogeneous factorisation time (copies included)"},
+           "roofline": None,
+           "gpu_only": {"ms": round(t_gpu, 2), "gflops": round(flops / (t_gpu * 1e-3) / 1e9, 1),
+                        "schedule": "chol_factor: panel width 8, lookahead"},
+           "best_share": best["gpu_share"],
+           "hetero_gain_vs_gpu_only": round((t_gpu - best["ms"]) / t_gpu, 4),
+           "curve": curve}
+    del host_ws
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(args.cpu_n or 12288)
     return out
 
 

@@ -82,7 +82,7 @@ typedef struct chol_factor_s *chol_handle;
  *                     solve from the current iterate;
  * CHOL_FALLBACK_SHIFT the FP16 form met a non-positive pivot and was
  *                     refactored with the diagonal shift c * 2^-11 added to
- *                     the scaled matrix (c = option "fp16_shift_c");
+ *                     the scaled matrix (c = option "fp16_shift_c", 32);
  * CHOL_FALLBACK_FP32  the FP16 form failed (again) and an FP32 factor
  *                     replaced it (chol_factor_precision then reports
  *                     CHOL_FP32).                                           */
@@ -355,8 +355,11 @@ void chol_profile_reset(void);
  * "pcg_recompute": chol_refine_solve's PCG takes the true residual every
  *                  this many iterations (default 50, the paper's periodic
  *                  recomputation; 0 = never).
- * "fp16_shift_c" : c of the FP16 form's shifted retry (default 8; 0 = go
+ * "fp16_shift_c" : c of the FP16 form's shifted retry (default 32; 0 = go
  *                  straight to the FP32 fallback).
+ * "host_threads" : threads of the heterogeneous factorisation's CPU share
+ *                  (default min(16, hardware threads); only before its first
+ *                  call).
  * "first_panel_width": tile columns of the first panel (1..16; 0 = the
  *                  panel width; default 0).  With lookahead the first
  *                  panel's tile columns are packed first and factored while
@@ -372,6 +375,71 @@ void chol_profile_reset(void);
  * Returns CHOL_OK or -1 (unknown key) / -2 (value out of range).         */
 int chol_set_option(const char *key, int64_t value);
 int64_t chol_get_option(const char *key);
+
+/* ---- heterogeneous CPU + GPU factorisation ------------------------------
+ * The paper's heterogeneous Cholesky (Implementation, "Cholesky
+ * implementation"; Results, the heterogeneous Cholesky workload
+ * distribution and its comparison with the homogeneous runs): FP64, tile
+ * 128, panels of panel_width tile columns (0 = 8).  A horizontal border
+ * splits the trailing matrix's tile rows: the rows above it (the diagonal
+ * tile included) are factored and updated by the host CPU (the library's
+ * own FP64 tile kernels on a pool of "host_threads" threads), the rows below
+ * it by the GPU.  Per panel the CPU factors the diagonal tiles and solves its
+ * rows, sends those tiles to the GPU (one copy per tile column), and both
+ * sides apply the Step-3 update to their rows; the CPU updates the next
+ * panel's columns first.  The border moves down as the trailing matrix
+ * shrinks, so that about a fraction gpu_share of the Step-3 tile updates is
+ * done by the GPU; each move copies whole tile rows from the GPU to the CPU.
+ * When the CPU's share drops below one panel its rows return to the GPU,
+ * which finishes alone.  gpu_share = 1 is the GPU alone (plain schedule,
+ * no lookahead).
+ * A, lda, n  : as chol_factor (device, column-major FP64, lower triangle).
+ * workspace  : device, >= chol_factor_bytes(n, CHOL_FP64, 128); holds the
+ *              factor afterwards (the handle works with chol_solve etc.).
+ * host_ws    : HOST memory, >= chol_hetero_host_bytes(n) bytes (the packed
+ *              triangle; pinned memory makes the copies asynchronous); it
+ *              holds the CPU's rows while they are worked on.
+ * info       : out (required): synchronous call, LAPACK-style info.
+ * rep        : out, may be NULL.
+ * Errors: -1 A NULL, -2 n < 0, -3 lda, -4 gpu_share outside [0, 1], -5
+ * panel_width outside [0, 8], -6 workspace NULL or misaligned,
+ * CHOL_ERR_WORKSPACE, -8 host_ws NULL or too small, -10 F NULL, -11 info
+ * NULL, CHOL_ERR_HIP.                                                      */
+typedef struct {
+  double gpu_share_target;  /* as requested                                  */
+  double gpu_share_tiles;   /* Step-3 tile updates (x panel columns) on the
+                               GPU over all of them                          */
+  double gpu_tile_updates, cpu_tile_updates;
+  double bytes_h2d, bytes_d2h; /* host <-> device copies                     */
+  double ms_total;          /* wall time of the call                         */
+  double ms_cpu;            /* host time in the CPU's tile kernels           */
+  double ms_wait_gpu;       /* host time waiting for the GPU                 */
+  int32_t border_shifts;    /* border moves (including the final handover)   */
+  int32_t handover_column;  /* tile column from which the GPU ran alone      */
+  int32_t cpu_threads;
+  int32_t reserved;
+} chol_hetero_report;
+
+size_t chol_hetero_host_bytes(int64_t n);
+int chol_factor_hetero(const double *A, int64_t n, int64_t lda, double gpu_share,
+                       int panel_width, void *workspace, size_t ws_bytes,
+                       double *host_ws, size_t host_bytes, chol_handle *F,
+                       int64_t *info, chol_hetero_report *rep, void *stream);
+
+/* Host tile kernels of the CPU share (128 x 128 column-major FP64 tiles,
+ * HOST pointers; no device work):
+ * chol_host_potrf_tile: in-place Cholesky of a lower tile, strict upper part
+ *   zeroed; returns 0 or the 1-based local column of the first non-positive
+ *   pivot (Step 1).
+ * chol_host_trsm_tile: X <- X L^{-T} by substitution (Step 2).
+ * chol_host_gemm_nt_tiles: C -= sum_{p < np} A[p] B[p]^T (Step 3); with
+ *   lower != 0 (a diagonal tile) the lower triangle, diagonal included, is
+ *   updated and the strict upper triangle is left unspecified, as on the
+ *   device.                                                                */
+int chol_host_potrf_tile(double *L);
+void chol_host_trsm_tile(const double *L, double *X);
+void chol_host_gemm_nt_tiles(double *C, const double *const *A, const double *const *B, int np,
+                             int lower);
 
 /* ---- conjugate gradients (the paper's iterative solver) ----------------
  * The CG method of the paper (Fundamentals, "The Conjugate Gradient

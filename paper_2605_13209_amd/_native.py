@@ -79,6 +79,12 @@ EXPORTS = {
     "chol_get_option": (_i64, [ctypes.c_char_p]),
     "chol_profile_read": (_int, [ctypes.POINTER(_dbl), ctypes.POINTER(_i64), ctypes.POINTER(_dbl)]),
     "chol_profile_reset": (None, []),
+    "chol_hetero_host_bytes": (_sz, [_i64]),
+    "chol_factor_hetero": (_int, [_vp, _i64, _i64, _dbl, _int, _vp, _sz, _vp, _sz, ctypes.POINTER(_vp),
+                                  ctypes.POINTER(_i64), _vp, _vp]),
+    "chol_host_potrf_tile": (_int, [_vp]),
+    "chol_host_trsm_tile": (None, [_vp, _vp]),
+    "chol_host_gemm_nt_tiles": (None, [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), _int, _int]),
     "cg_workspace_bytes": (_sz, [_i64, _int, _i64]),
     "cg_solve": (_int, [_vp, _i64, _i64, _int, _vp, _i64, _vp, _i64, _i64, _dbl, _i64, _i64, _vp, _sz,
                         ctypes.POINTER(_i64), ctypes.POINTER(_dbl), _vp]),
@@ -336,6 +342,56 @@ def chol_refine_solve_noalloc(F: Factor, B: torch.Tensor, out: torch.Tensor, *, 
 
 def chol_refine_noalloc_max_bytes() -> int:
     return int(lib().chol_refine_noalloc_max_bytes())
+
+
+class HeteroReport(ctypes.Structure):
+    _fields_ = [("gpu_share_target", ctypes.c_double), ("gpu_share_tiles", ctypes.c_double),
+                ("gpu_tile_updates", ctypes.c_double), ("cpu_tile_updates", ctypes.c_double),
+                ("bytes_h2d", ctypes.c_double), ("bytes_d2h", ctypes.c_double),
+                ("ms_total", ctypes.c_double), ("ms_cpu", ctypes.c_double), ("ms_wait_gpu", ctypes.c_double),
+                ("border_shifts", ctypes.c_int32), ("handover_column", ctypes.c_int32),
+                ("cpu_threads", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
+def chol_hetero_host_bytes(n: int) -> int:
+    return int(lib().chol_hetero_host_bytes(int(n)))
+
+
+def chol_factor_hetero(A: torch.Tensor, gpu_share: float, *, panel_width: int = 0,
+                       workspace: torch.Tensor | None = None, host_ws: torch.Tensor | None = None,
+                       stream=None, raise_not_spd: bool = True):
+    """Heterogeneous CPU + GPU FP64 factorisation (tile 128); returns (Factor,
+    report dict).  host_ws: a host uint8/float64 tensor of at least
+    chol_hetero_host_bytes(n) bytes (pinned for asynchronous copies)."""
+    _need_device(A, "A")
+    n = A.shape[0]
+    need = chol_factor_bytes(n, CHOL_FP64, 128)
+    if workspace is None:
+        workspace = torch.empty(need, dtype=torch.uint8, device=A.device)
+    hb = chol_hetero_host_bytes(n)
+    if host_ws is None:
+        host_ws = torch.empty(max(hb, 8), dtype=torch.uint8, pin_memory=True)
+    if host_ws.is_cuda:
+        raise ValueError("host_ws must be host memory")
+    h = _vp()
+    info = _i64(0)
+    rep = HeteroReport()
+    st = _stream(stream)
+    rc = lib().chol_factor_hetero(A.data_ptr(), n, _ld(A), float(gpu_share), int(panel_width),
+                                  workspace.data_ptr(), workspace.numel() * workspace.element_size(),
+                                  host_ws.data_ptr(), host_ws.numel() * host_ws.element_size(), ctypes.byref(h),
+                                  ctypes.byref(info), ctypes.byref(rep), st)
+    _check(rc, "chol_factor_hetero")
+    F = Factor(h, workspace, st)
+    if raise_not_spd and info.value != 0:
+        F.free()
+        e = CholError(CHOL_ERR_NOT_SPD, "chol_factor_hetero")
+        e.info = int(info.value)
+        raise e
+    return F, rep.as_dict()
 
 
 def chol_residual(A: torch.Tensor, X: torch.Tensor, B: torch.Tensor, out: torch.Tensor | None = None,

@@ -21,7 +21,7 @@ LIB = os.path.join(PKG, "libchol_mi355x.so")
 ARCH = os.environ.get("CHOL_OFFLOAD_ARCH", "gfx950")
 
 SOURCES = ["assemble.hip", "pack.hip", "potrf_trsm.hip", "update.hip", "trsv.hip", "blas1.hip",
-           "cg.hip", "chol_api.cpp", "cg_api.cpp"]
+           "cg.hip", "chol_api.cpp", "cg_api.cpp", "hetero.cpp", "host_tiles.cpp"]
 
 # Packed FP32 VALU instructions are disabled for every device pass.
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Wall", "-Wno-unused-function",
@@ -52,7 +52,7 @@ def build(verbose: bool = False) -> str:
     with cf.ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [hipcc(), "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, "-o", tmp]
+    cmd = [hipcc(), "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, "-lpthread", "-o", tmp]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError(f"link failed: {' '.join(cmd)}\n{res.stdout}\n{res.stderr}")

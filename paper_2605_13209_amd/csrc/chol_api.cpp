@@ -26,20 +26,14 @@
 #include <vector>
 
 #include "../../include/chol.h"
+#include "factor_handle.hpp"
+#include "host_tiles.hpp"
 #include "internal.hpp"
 
 using namespace chol;
 
 namespace {
 
-// Start of the factor workspace: the info word (offset 0), the largest
-// diagonal entry for the FP16 form's scaling (offset 64), and the solves'
-// synchronisation words (offset kSolveSyncOff, kSolveSyncWords ints: an
-// abort word and per-chunk progress counters, cleared by a kernel before
-// every solve).
-constexpr size_t kHeader = 512;
-constexpr size_t kSolveSyncOff = 256;
-constexpr int64_t kSolveSyncWords = 64;
 
 struct Options {
   std::atomic<int64_t> panel_width{0};  // 0: automatic
@@ -52,7 +46,7 @@ struct Options {
   std::atomic<int64_t> f16_wide{1};  // FP16 whole-triangle update with 2 x 2 tiles per workgroup
   std::atomic<int64_t> solve_spin_max{1 << 20};  // bound of each wait inside a solve
   std::atomic<int64_t> pcg_recompute{50};  // PCG: true residual every this many iterations
-  std::atomic<int64_t> fp16_shift_c{8};    // FP16 retry: diagonal shift c * 2^-11 (0 = no retry)
+  std::atomic<int64_t> fp16_shift_c{32};   // FP16 retry: diagonal shift c * 2^-11 (0 = no retry)
 };
 Options g_opt;
 
@@ -212,32 +206,6 @@ bool tile_ok(int tile) { return tile == 64 || tile == 128; }
 
 }  // namespace
 
-struct chol_factor_s {
-  int64_t n = 0, N = 0;
-  int b = 0, precision = 0, device = 0;
-  void *tiles = nullptr;
-  void *dinv = nullptr;  // inverted diagonal blocks L_cc^{-T} (the solves)
-  void *p16 = nullptr;   // CHOL_FP16_SCALED: two FP16 panel buffers (alternating panels)
-  int64_t *d_info = nullptr;
-  int *sync = nullptr;   // the solves' synchronisation words (workspace header)
-  double scale = 1.0;  // CHOL_FP16_SCALED: the factor of A / scale (+ shift I) is stored
-  double shift = 0.0;  // CHOL_FP16_SCALED retry: diagonal shift added to A / scale
-  int fallback = 0;    // CHOL_FALLBACK_SHIFT / CHOL_FALLBACK_FP32 taken by chol_factor
-  hipStream_t stream = nullptr;
-  int64_t info = -1;  // host copy once known
-  // Solves share the synchronisation words: a solve on another stream than
-  // the previous one waits for it (event recorded after every solve).
-  // The mutex makes that check, the launches and the record one step when
-  // several host threads solve with the handle.
-  std::mutex solve_mu;
-  hipEvent_t ev_solve = nullptr;
-  hipStream_t last_solve = nullptr;
-  bool solved = false;
-  ~chol_factor_s() {
-    if (ev_solve) (void)hipEventDestroy(ev_solve);
-  }
-};
-
 #define HIP_OK(x)                              \
   do {                                         \
     if ((x) != hipSuccess) return CHOL_ERR_HIP; \
@@ -296,6 +264,9 @@ int chol_set_option(const char *key, int64_t value) {
   } else if (!strcmp(key, "fp16_shift_c")) {
     if (value < 0 || value > 1024) return -2;
     g_opt.fp16_shift_c = value;
+  } else if (!strcmp(key, "host_threads")) {
+    if (value < 1 || value > 1024) return -2;
+    host::set_threads((int)value);
   } else {
     return -1;
   }
@@ -315,6 +286,7 @@ int64_t chol_get_option(const char *key) {
   if (!strcmp(key, "solve_spin_max")) return g_opt.solve_spin_max;
   if (!strcmp(key, "pcg_recompute")) return g_opt.pcg_recompute;
   if (!strcmp(key, "fp16_shift_c")) return g_opt.fp16_shift_c;
+  if (!strcmp(key, "host_threads")) return host::threads();
   return -1;
 }
 
@@ -404,6 +376,27 @@ static void factor_panel(chol_factor_s *F, size_t p, int64_t c0, int64_t c1, int
   }
   if (F->p16) launch_panel_f16(F->tiles, N, c0, (int)(c1 - c0), panel_buf(F, p), F->d_info, s);
 }
+
+// The plain schedule (no lookahead) from tile column c_start on, for a
+// matrix already packed whose columns left of c_start are final and whose
+// trailing part has received their updates; then the inverted diagonal
+// blocks.  Used by the heterogeneous driver once the CPU's share is done.
+}  // extern "C"
+namespace chol {
+int enqueue_factor_tail(chol_factor_s *F, int64_t c_start, int64_t w, int S, hipStream_t s) {
+  const int64_t N = F->N;
+  const int st = store_of(F->precision);
+  for (int64_t c0 = c_start; c0 < N; c0 += w) {
+    const int64_t c1 = std::min<int64_t>(c0 + w, N);
+    factor_panel(F, 0, c0, c1, st, s);
+    if (c1 < N)
+      update(F->tiles, st, F->b, N, c0, (int)(c1 - c0), c1, N, /*tri*/ 0, S, 0, F->d_info, s);
+  }
+  launch_diag_inverse(F->tiles, st, F->b, N, F->dinv, F->d_info, s);
+  return hipGetLastError() == hipSuccess ? CHOL_OK : CHOL_ERR_HIP;
+}
+}  // namespace chol
+extern "C" {
 
 // Enqueue the whole factorisation (clear info, pack, column steps) on the
 // factor's stream and, with lookahead, the side stream joined back into it.

@@ -57,19 +57,22 @@ void launch_unpack(const void *tiles, int store, int b, int64_t N, int64_t n, do
 // Step 1: factor diagonal tile c in place (FP64 arithmetic).  Sets *info.
 void launch_potrf(void *tiles, int store, int b, int64_t N, int64_t c, int64_t *info,
                   hipStream_t s);
-// Step 2: tiles (i, c), i in [c+1, N): X <- X L_cc^{-T} (FP64 arithmetic).
+// Step 2: tiles (i, c), i in [r0, N) (r0 <= 0: c + 1): X <- X L_cc^{-T}
+// (FP64 arithmetic).
 void launch_trsm(void *tiles, int store, int b, int64_t N, int64_t c, const int64_t *info,
-                 hipStream_t s);
+                 hipStream_t s, int64_t r0 = 0);
 // Step 3: C_ik -= sum_{p in [p0, p0+pw)} L_ip L_kp^T over the region
 //   mode 0 (triangle): k0 <= k <= i < N;
-//   mode 1 (band)    : k in [k0, k1), k <= i < N  (k1 - k0 <= super_tile).
+//   mode 1 (band)    : k in [k0, k1), k <= i < N  (k1 - k0 <= super_tile);
+//   mode 2 (rectangle, FP64 tile 128): i in [r0, N), k in [k0, k1), r0 >= k1.
 // fp16 = 1 takes the panel operands in FP16 from p16, the panel converted
 // by launch_panel_f16 (FP32 storage, tile 128 only).
 // max_wg > 0 caps the number of workgroups (each then walks several tiles),
 // leaving workgroup slots free for kernels on other streams.
 void launch_update(void *tiles, int store, int b, int64_t N, int64_t p0, int pw, int64_t k0,
                    int64_t k1, int mode, int super_tile, int fp16, const int64_t *info,
-                   hipStream_t s, int64_t max_wg = 0, const void *p16 = nullptr);
+                   hipStream_t s, int64_t max_wg = 0, const void *p16 = nullptr,
+                   int64_t r0 = 0);
 // Kernel choice for the FP16 form's whole-triangle updates (1: 2 x 2 tiles
 // per workgroup, the default; 0: one tile per workgroup).  Same result.
 void set_f16_wide(int on);

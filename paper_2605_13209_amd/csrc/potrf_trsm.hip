@@ -372,9 +372,9 @@ __device__ __forceinline__ void trsm_tile(const T *__restrict__ L, T *__restrict
 
 template <int B, typename T>
 __global__ __launch_bounds__(256) void trsm_kernel(T *__restrict__ tiles, int64_t N, int64_t c,
-                                                   const int64_t *__restrict__ info) {
+                                                   int64_t r0, const int64_t *__restrict__ info) {
   if (*info != 0) return;
-  const int64_t i = c + 1 + blockIdx.x;
+  const int64_t i = r0 + blockIdx.x;
   trsm_tile<B, T, false>(tiles + tile_index(c, c, N) * (int64_t)(B * B),
                          tiles + tile_index(i, c, N) * (int64_t)(B * B));
 }
@@ -403,15 +403,16 @@ void potrf_dispatch(void *tiles, int store, int64_t N, int64_t c, int64_t *info,
 
 template <int B>
 void trsm_dispatch(void *tiles, int store, int64_t N, int64_t c, const int64_t *info,
-                   hipStream_t s) {
-  const int64_t nt = N - c - 1;
+                   hipStream_t s, int64_t r0) {
+  if (r0 <= c) r0 = c + 1;
+  const int64_t nt = N - r0;
   if (nt <= 0) return;
   if (store == STORE_F64)
     hipLaunchKernelGGL((trsm_kernel<B, double>), dim3((unsigned)nt), dim3(256), 0, s,
-                       (double *)tiles, N, c, info);
+                       (double *)tiles, N, c, r0, info);
   else
     hipLaunchKernelGGL((trsm_kernel<B, float>), dim3((unsigned)nt), dim3(256), 0, s,
-                       (float *)tiles, N, c, info);
+                       (float *)tiles, N, c, r0, info);
 }
 
 }  // namespace
@@ -447,11 +448,11 @@ void launch_diag_inverse(const void *tiles, int store, int b, int64_t N, void *d
 }
 
 void launch_trsm(void *tiles, int store, int b, int64_t N, int64_t c, const int64_t *info,
-                 hipStream_t s) {
+                 hipStream_t s, int64_t r0) {
   if (b == 128)
-    trsm_dispatch<128>(tiles, store, N, c, info, s);
+    trsm_dispatch<128>(tiles, store, N, c, info, s, r0);
   else
-    trsm_dispatch<64>(tiles, store, N, c, info, s);
+    trsm_dispatch<64>(tiles, store, N, c, info, s, r0);
 }
 
 }  // namespace chol

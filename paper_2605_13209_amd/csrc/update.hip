@@ -204,6 +204,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void u
 //                      of chunk s+1 has landed), then DMA chunk s+2 into
 //                      the buffer chunk s used;
 //   step 3 of chunk s: read the first fragments of chunk s+1.
+// REGION 2 (rectangle, used by the heterogeneous factorisation): tiles
+// (k0 + S + t / K, k0 + t mod K), i.e. rows [k0 + S, N) by columns
+// [k0, k0 + K), S then being the row offset instead of the super-tile side.
 template <int REGION>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void update_f64_kernel(
     double *__restrict__ tiles, int64_t N, int64_t p0, int pw, int64_t k0, int64_t K, int S,
@@ -223,10 +226,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void u
     const int64_t t = (blockIdx.x % 8) * G8 + pos;
     if (t >= G) break;
     int64_t ir, kr;
-    if (REGION == 0)
+    if (REGION == 0) {
       map_triangle(t, N - k0, S, ir, kr);
-    else
+    } else if (REGION == 1) {
       map_band(t, K, ir, kr);
+    } else {
+      ir = S + t / K;
+      kr = t % K;
+    }
     const int64_t i = k0 + ir, k = k0 + kr;
     double *C = tiles + tile_index(i, k, N) * (int64_t)(BT * BT);
     const int nstage = pw * (BT / KC);
@@ -657,10 +664,18 @@ void set_f16_wide(int on) { g_f16_wide = on ? 1 : 0; }
 
 void launch_update(void *tiles, int store, int b, int64_t N, int64_t p0, int pw, int64_t k0,
                    int64_t k1, int mode, int super_tile, int fp16, const int64_t *info,
-                   hipStream_t s, int64_t max_wg, const void *p16) {
+                   hipStream_t s, int64_t max_wg, const void *p16, int64_t r0) {
   const int64_t R = N - k0;
   if (R <= 0 || pw <= 0) return;
   const int64_t K = k1 - k0;
+  if (mode == 2) {
+    // rectangle rows [r0, N) x columns [k0, k1), FP64 tile 128 only
+    if (K <= 0 || r0 < k1 || r0 >= N || b != BT || store != STORE_F64 || fp16) return;
+    const int64_t G = (N - r0) * K, G8 = (G + 7) / 8;
+    hipLaunchKernelGGL(update_f64_kernel<2>, dim3((unsigned)(8 * G8)), dim3(256), 0, s,
+                       (double *)tiles, N, p0, pw, k0, K, (int)(r0 - k0), G, G8, info);
+    return;
+  }
   int64_t G;
   if (mode == 0) {
     G = triangle_count(R);
