@@ -254,7 +254,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="headline_n65536",
                     choices=["headline_n65536", "fp64_n32768", "fp64_n1024", "fp64_n65536", "mixed_n65536",
-                             "mixed_fp16_n131072", "serve", "cg_n65536", "hetero"])
+                             "mixed_fp16_n131072", "serve", "cg_n65536", "hetero", "cg_hetero"])
     ap.add_argument("--shares", default="1.0,0.999,0.997,0.995,0.99,0.98,0.95,0.9",
                     help="hetero: GPU shares of the Step-3 tiles to sweep")
     ap.add_argument("--no-sub", action="store_true",
@@ -314,6 +314,8 @@ def main():
         out = bench_cg(args)
     elif wl == "hetero":
         out = bench_hetero(args)
+    elif wl == "cg_hetero":
+        out = bench_cg_hetero(args)
     elif wl == "headline_n65536":
         out = bench_headline(args)
         if not args.no_cpu_baseline:
@@ -572,6 +574,80 @@ def bench_hetero(args):
     del host_ws
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_n or 12288)
+    return out
+
+
+def bench_cg_hetero(args):
+    """The paper's heterogeneous CG against the GPU alone (its CG workload:
+    eps = 1e-6, recomputation every 50 iterations, no iteration cap): SE
+    kernel d=8, lengthscale 1, variance 1, noise 0.1, n = 65536, one
+    right-hand side, A resident in HBM.  For each GPU share of the stored
+    tiles in --shares, cg_solve_hetero is timed (packing and the copies of
+    the CPU's tiles included, as cg_solve packs too); the GPU-alone line is
+    cg_solve.  value = n^3/3 over the best heterogeneous time (the unit of
+    the Cholesky lines)."""
+    import torch
+    import gp_inputs
+    import paper_2605_13209_amd as P
+    n = args.n or 65536
+    eps, recompute = 1e-6, 50
+    steps = args.steps if args.steps != 10 else 2
+    X, B = gp_inputs.gp_problem(n, d=8, k=1, seed=0)
+    Xd = torch.from_numpy(X).cuda()
+    Bd = P.to_colmajor(torch.from_numpy(B))
+    A = P.colmajor_empty(n, n)
+    P.gp_assemble(Xd, *HP, full=False, out=A)
+    shares = [float(v) for v in (args.shares if args.shares != "1.0,0.999,0.997,0.995,0.99,0.98,0.95,0.9"
+                                 else "1.0,0.995,0.99,0.98,0.97,0.95").split(",")]
+    ws = torch.empty(max(P.cg_workspace_bytes(n, 1, 128), P.lib().cg_hetero_workspace_bytes(n)),
+                     dtype=torch.uint8, device="cuda")
+    host_ws = torch.empty(max(P.lib().cg_hetero_host_bytes(n, s) for s in shares), dtype=torch.uint8,
+                          pin_memory=True)
+    Xs = P.colmajor_empty(n, 1)
+
+    def timed(fn):
+        ts, res = [], None
+        for r in range(1 + steps):
+            Xs.zero_()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            res = fn()
+            torch.cuda.synchronize()
+            if r >= 1:
+                ts.append((time.perf_counter() - t0) * 1e3)
+        return float(np.mean(ts)), res
+
+    t_gpu, g = timed(lambda: P.cg_solve(A, Bd, X=Xs, eps=eps, max_iter=100000, recompute=recompute, tile=128,
+                                        workspace=ws))
+    curve = []
+    for share in shares:
+        t, (x, it, rr, conv, rep) = timed(lambda: P.cg_solve_hetero(A, Bd[:, 0], share, X=Xs[:, 0], eps=eps,
+                                                                    max_iter=100000, recompute=recompute,
+                                                                    workspace=ws, host_ws=host_ws))
+        R = P.chol_residual(A, Xs, Bd)
+        curve.append({"gpu_share": share, "ms": round(t, 2), "iterations": it, "converged": conv,
+                      "ms_per_iteration": round(t / max(it, 1), 4),
+                      "gpu_share_tiles": round(rep["gpu_share_tiles"], 5), "gpu_rows": rep["gpu_rows"],
+                      "ms_cpu": round(rep["ms_cpu"], 1), "ms_wait_gpu": round(rep["ms_wait_gpu"], 1),
+                      "gb_h2d": round(rep["bytes_h2d"] / 1e9, 3), "gb_d2h": round(rep["bytes_d2h"] / 1e9, 3),
+                      "relres_true": float(torch.linalg.norm(R) / torch.linalg.norm(Bd)),
+                      "cpu_threads": rep["cpu_threads"]})
+        print(f"bench: cg hetero n={n} share={share} {t:.1f} ms, {it} iterations", file=sys.stderr, flush=True)
+    best = min(curve, key=lambda c: c["ms"])
+    out = {"metric": METRIC, "value": round(n ** 3 / 3 / (best["ms"] * 1e-3) / 1e9, 2), "unit": "GFLOP/s",
+           "n_gpus": 1, "steps": steps, "warmup": 1, "ms_per_step": best["ms"], "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": f"hetero_cpu_gpu_cg_n{n}", "n": n, "tile": 128, "rhs": 1, "eps": eps,
+                      "recompute": recompute, "kernel": "SE d=8 lengthscale=1 variance=1 noise=0.1", "seed": 0,
+                      "value_is": "n^3/3 / best heterogeneous CG time to solution"},
+           "roofline": None,
+           "gpu_only": {"ms": round(t_gpu, 2), "iterations": int(g.iters[0]),
+                        "ms_per_iteration": round(t_gpu / max(g.iters[0], 1), 4)},
+           "best_share": best["gpu_share"], "hetero_gain_vs_gpu_only": round((t_gpu - best["ms"]) / t_gpu, 4),
+           "curve": curve}
+    del host_ws
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline_cg(args.cpu_n or 10240, eps)
     return out
 
 

@@ -480,6 +480,57 @@ int cg_solve(const double *A, int64_t n, int64_t lda, int tile, const double *B,
              int64_t recompute, void *workspace, size_t ws_bytes, int64_t *iters,
              double *relres, void *stream);
 
+/* ---- heterogeneous CPU + GPU conjugate gradients -----------------------
+ * The paper's heterogeneous CG (Implementation, "CG implementation";
+ * Results, the heterogeneous CG workload distribution and its comparison
+ * with the homogeneous runs): the CG iteration of cg_solve (one right-hand
+ * side, FP64, tile 128) with the packed lower-tile matrix and every vector
+ * split horizontally at a tile row S.  The GPU owns the rows above the
+ * split and streams the tiles of its leading S x S triangle; the host CPU
+ * owns the rows below and streams all tiles of its rows (its triangle and
+ * the rectangle left of it, whose transposed products it sends to the GPU
+ * as one vector per product).  Per iteration the two partial sums of s.t
+ * and of r.r cross to the host (and the CPU's to the device, so that both
+ * sides form the same scalars in the same order), and the two halves of s
+ * change sides; an iteration that recomputes the true residual also
+ * exchanges x.  S is the largest tile row with S (S + 1) / 2 <= gpu_share
+ * N (N + 1) / 2 (gpu_share: the fraction of the stored tiles in the GPU's
+ * triangle; 1 = the GPU alone, 0 = the CPU alone).
+ * A, lda      : device, n x n column-major FP64 (lower triangle read),
+ *               packed into the workspace at the start of the call.
+ * B, X        : device, n FP64 each; X holds the starting guess on entry and
+ *               the final iterate on exit.
+ * eps, max_iter, recompute: as cg_solve.
+ * workspace   : device, 256-byte aligned, >= cg_hetero_workspace_bytes(n).
+ * host_ws     : HOST memory (pinned makes the copies asynchronous), >=
+ *               cg_hetero_host_bytes(n, gpu_share): the CPU's tiles, their
+ *               products and the host halves of the vectors.
+ * iters, relres: out (host), may be NULL: iterations, sqrt(u / u0) at exit.
+ * rep         : out, may be NULL.
+ * Synchronous.  Returns CHOL_OK, CHOL_ERR_NOT_CONVERGED (max_iter reached),
+ * -1 A, -2 n, -3 lda, -4 B or X NULL, -6 eps, -7 max_iter, -8 recompute,
+ * -9 gpu_share outside [0, 1], -10 workspace, CHOL_ERR_WORKSPACE, -12
+ * host_ws, CHOL_ERR_HIP.                                                   */
+typedef struct {
+  double gpu_share_target;  /* as requested                                  */
+  double gpu_share_tiles;   /* stored tiles in the GPU's triangle / all       */
+  double bytes_h2d, bytes_d2h;
+  double ms_total;          /* wall time of the call                          */
+  double ms_cpu;            /* host time in the CPU's tile products           */
+  double ms_wait_gpu;       /* host time waiting for the GPU                  */
+  int32_t iterations;
+  int32_t recomputations;
+  int32_t gpu_rows;         /* S, tile rows on the GPU                        */
+  int32_t cpu_threads;
+} cg_hetero_report;
+
+size_t cg_hetero_workspace_bytes(int64_t n);
+size_t cg_hetero_host_bytes(int64_t n, double gpu_share);
+int cg_solve_hetero(const double *A, int64_t n, int64_t lda, const double *B, double *X,
+                    double eps, int64_t max_iter, int64_t recompute, double gpu_share,
+                    void *workspace, size_t ws_bytes, void *host_ws, size_t host_bytes,
+                    int64_t *iters, double *relres, cg_hetero_report *rep, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

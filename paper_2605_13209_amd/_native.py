@@ -82,6 +82,10 @@ EXPORTS = {
     "chol_hetero_host_bytes": (_sz, [_i64]),
     "chol_factor_hetero": (_int, [_vp, _i64, _i64, _dbl, _int, _vp, _sz, _vp, _sz, ctypes.POINTER(_vp),
                                   ctypes.POINTER(_i64), _vp, _vp]),
+    "cg_hetero_workspace_bytes": (_sz, [_i64]),
+    "cg_hetero_host_bytes": (_sz, [_i64, _dbl]),
+    "cg_solve_hetero": (_int, [_vp, _i64, _i64, _vp, _vp, _dbl, _i64, _i64, _dbl, _vp, _sz, _vp, _sz,
+                               ctypes.POINTER(_i64), ctypes.POINTER(_dbl), _vp, _vp]),
     "chol_host_potrf_tile": (_int, [_vp]),
     "chol_host_trsm_tile": (None, [_vp, _vp]),
     "chol_host_gemm_nt_tiles": (None, [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), _int, _int]),
@@ -392,6 +396,47 @@ def chol_factor_hetero(A: torch.Tensor, gpu_share: float, *, panel_width: int = 
         e.info = int(info.value)
         raise e
     return F, rep.as_dict()
+
+
+class CgHeteroReport(ctypes.Structure):
+    _fields_ = [("gpu_share_target", ctypes.c_double), ("gpu_share_tiles", ctypes.c_double),
+                ("bytes_h2d", ctypes.c_double), ("bytes_d2h", ctypes.c_double), ("ms_total", ctypes.c_double),
+                ("ms_cpu", ctypes.c_double), ("ms_wait_gpu", ctypes.c_double), ("iterations", ctypes.c_int32),
+                ("recomputations", ctypes.c_int32), ("gpu_rows", ctypes.c_int32), ("cpu_threads", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+def cg_solve_hetero(A: torch.Tensor, b: torch.Tensor, gpu_share: float, *, X: torch.Tensor | None = None,
+                    eps: float = 1e-6, max_iter: int = 100000, recompute: int = 50,
+                    workspace: torch.Tensor | None = None, host_ws: torch.Tensor | None = None, stream=None):
+    """Heterogeneous CPU + GPU CG for one right-hand side b (device, n or n x 1).
+    Returns (X, iterations, relres, converged, report dict)."""
+    _need_device(A, "A")
+    _need_device(b, "b")
+    n = A.shape[0]
+    if X is None:
+        X = torch.zeros(n, dtype=torch.float64, device=A.device)
+    need = int(lib().cg_hetero_workspace_bytes(n))
+    if workspace is None:
+        workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=A.device)
+    hb = int(lib().cg_hetero_host_bytes(n, float(gpu_share)))
+    if host_ws is None:
+        host_ws = torch.empty(max(hb, 8), dtype=torch.uint8, pin_memory=True)
+    if host_ws.is_cuda:
+        raise ValueError("host_ws must be host memory")
+    it = _i64(0)
+    rr = ctypes.c_double(0.0)
+    rep = CgHeteroReport()
+    rc = lib().cg_solve_hetero(A.data_ptr(), n, _ld(A), b.data_ptr(), X.data_ptr(), float(eps), int(max_iter),
+                               int(recompute), float(gpu_share), workspace.data_ptr(),
+                               workspace.numel() * workspace.element_size(), host_ws.data_ptr(),
+                               host_ws.numel() * host_ws.element_size(), ctypes.byref(it), ctypes.byref(rr),
+                               ctypes.byref(rep), _stream(stream))
+    if rc not in (0, CHOL_ERR_NOT_CONVERGED):
+        _check(rc, "cg_solve_hetero")
+    return X, int(it.value), float(rr.value), rc == 0, rep.as_dict()
 
 
 def chol_residual(A: torch.Tensor, X: torch.Tensor, B: torch.Tensor, out: torch.Tensor | None = None,

@@ -71,19 +71,22 @@ __device__ inline void colsum_step(double (&v)[CW], int lane) {
 // row-block product A_ic s_c (rows of block i), side 1 the transposed
 // product A_ic^T s_i (rows of block c).  A diagonal tile writes the full
 // symmetric product of its block (lower part mirrored) to side 0 only.
+// The grid covers the leading Nt x Nt tiles (Nt = N: all of them; the
+// heterogeneous CG gives the GPU the leading block rows): workgroup w takes
+// tile w of the Nt-triangle's packed order, stored at its N-packed id.
 template <int B>
 __global__ __launch_bounds__(kCgThreads) void symv_tiles_kernel(
-    const double *__restrict__ tiles, int64_t N, const double *__restrict__ v, int64_t ldv, int K,
-    double *__restrict__ part) {
+    const double *__restrict__ tiles, int64_t N, int64_t Nt, const double *__restrict__ v,
+    int64_t ldv, int K, double *__restrict__ part) {
   constexpr int R = B / 64;         // rows per lane
   constexpr int CW = B / kCgWaves;  // columns per wave
   extern __shared__ double sv[];  // [2][K][B]: s_c, then s_i
   __shared__ double red[kCgWaves][B];
   __shared__ double pcol[B];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int64_t id = blockIdx.x;
   int64_t i, c;
-  tile_of(id, N, i, c);
+  tile_of(blockIdx.x, Nt, i, c);
+  const int64_t id = tile_index(i, c, N);
   const double *T = tiles + id * (int64_t)B * B;
 
   // the wave's CW columns, R rows per lane: one contiguous column per wave
@@ -174,24 +177,26 @@ __device__ inline double block_sum(double x, double *sh) {
 
 
 // One workgroup per block row i: y = sum over the row's N partials in the
-// order c = 0..i (side 0 of tile (i, c)), then q = i+1..N-1 (side 1 of tile
+// order c = 0..i (side 0 of tile (i, c)), then q = i+1..Nt-1 (side 1 of tile
 // (q, i)); G thread groups take contiguous ranges, combined in group order.
+// Nt < N (heterogeneous CG): the products of tiles in rows >= Nt reach these
+// rows through `extra` (n_pad x K, ld), added last.
 //   CG_RED_T     t_i = y;                         pdot = s_i . t_i
 //   CG_RED_RESID r_i = b_i - y (active columns);  pdot = r_i . r_i
 //   CG_RED_INIT  r_i = s_i = b_i - y;             pdot = r_i . r_i
 template <int B>
 __global__ __launch_bounds__(kRedThreads) void symv_reduce_kernel(
-    const double *__restrict__ part, int64_t N, int K, int mode, double *__restrict__ t,
+    const double *__restrict__ part, int64_t N, int64_t Nt, int K, int mode, double *__restrict__ t,
     double *__restrict__ s, double *__restrict__ r, const double *__restrict__ bv, int64_t ld,
-    const int *__restrict__ act, double *__restrict__ pdot) {
+    const int *__restrict__ act, double *__restrict__ pdot, const double *__restrict__ extra) {
   constexpr int G = kRedThreads / B;
   __shared__ double gsum[G][B];
   __shared__ double sh[kRedThreads];
   const int64_t i = blockIdx.x;
   const int row = threadIdx.x % B, g = threadIdx.x / B;
   const int64_t stride = (int64_t)K * B;
-  const int64_t per = (N + G - 1) / G;
-  const int64_t e0 = g * per, e1 = (e0 + per < N) ? e0 + per : N;
+  const int64_t per = (Nt + G - 1) / G;
+  const int64_t e0 = g * per, e1 = (e0 + per < Nt) ? e0 + per : Nt;
   for (int k = 0; k < K; ++k) {
     double acc = 0.0;
 #pragma unroll 8
@@ -208,6 +213,7 @@ __global__ __launch_bounds__(kRedThreads) void symv_reduce_kernel(
 #pragma unroll
       for (int q = 1; q < G; ++q) y += gsum[q][row];
       const int64_t o = (int64_t)k * ld + i * B + row;
+      if (extra) y += extra[o];
       if (mode == CG_RED_T) {
         t[o] = y;
         dot = s[o] * y;
@@ -340,46 +346,54 @@ unsigned copy_grid(int64_t tot) {
 }  // namespace
 
 void launch_cg_symv(const double *tiles, int b, int64_t N, const double *v, int64_t ldv, int K,
-                    double *part, hipStream_t s) {
-  const unsigned grid = (unsigned)tile_count(N);
+                    double *part, hipStream_t s, int64_t Nt) {
+  if (Nt < 0 || Nt > N) Nt = N;
+  const unsigned grid = (unsigned)tile_count(Nt);
+  if (grid == 0) return;
   if (b == 128)
-    hipLaunchKernelGGL(symv_tiles_kernel<128>, dim3(grid), dim3(kCgThreads), 2 * K * 128 * 8, s, tiles, N, v, ldv,
-                       K, part);
+    hipLaunchKernelGGL(symv_tiles_kernel<128>, dim3(grid), dim3(kCgThreads), 2 * K * 128 * 8, s, tiles, N, Nt,
+                       v, ldv, K, part);
   else
-    hipLaunchKernelGGL(symv_tiles_kernel<64>, dim3(grid), dim3(kCgThreads), 2 * K * 64 * 8, s, tiles, N, v, ldv, K,
-                       part);
+    hipLaunchKernelGGL(symv_tiles_kernel<64>, dim3(grid), dim3(kCgThreads), 2 * K * 64 * 8, s, tiles, N, Nt,
+                       v, ldv, K, part);
 }
 
 void launch_cg_reduce(const double *part, int b, int64_t N, int K, int mode, double *t, double *sv,
                       double *r, const double *bv, int64_t ld, const int *act, double *pdot,
-                      hipStream_t s) {
+                      hipStream_t s, int64_t Nt, const double *extra) {
+  if (Nt < 0 || Nt > N) Nt = N;
+  if (Nt == 0) return;
   if (b == 128)
-    hipLaunchKernelGGL(symv_reduce_kernel<128>, dim3((unsigned)N), dim3(kRedThreads), 0, s, part, N,
-                       K, mode, t, sv, r, bv, ld, act, pdot);
+    hipLaunchKernelGGL(symv_reduce_kernel<128>, dim3((unsigned)Nt), dim3(kRedThreads), 0, s, part, N,
+                       Nt, K, mode, t, sv, r, bv, ld, act, pdot, extra);
   else
-    hipLaunchKernelGGL(symv_reduce_kernel<64>, dim3((unsigned)N), dim3(kRedThreads), 0, s, part, N,
-                       K, mode, t, sv, r, bv, ld, act, pdot);
+    hipLaunchKernelGGL(symv_reduce_kernel<64>, dim3((unsigned)Nt), dim3(kRedThreads), 0, s, part, N,
+                       Nt, K, mode, t, sv, r, bv, ld, act, pdot, extra);
 }
 
 void launch_cg_xr(int b, int64_t N, int K, const double *pdot, const double *u_in, const int *act,
                   double *x, double *r, const double *sv, const double *t, int64_t ld,
-                  int recompute_now, double *prr, hipStream_t s) {
+                  int recompute_now, double *prr, hipStream_t s, int64_t rows) {
+  if (rows < 0 || rows > N) rows = N;
+  if (rows == 0) return;
   if (b == 128)
-    hipLaunchKernelGGL(cg_xr_kernel<128>, dim3((unsigned)N), dim3(128), 0, s, N, K, pdot, u_in, act,
+    hipLaunchKernelGGL(cg_xr_kernel<128>, dim3((unsigned)rows), dim3(128), 0, s, N, K, pdot, u_in, act,
                        x, r, sv, t, ld, recompute_now, prr);
   else
-    hipLaunchKernelGGL(cg_xr_kernel<64>, dim3((unsigned)N), dim3(64), 0, s, N, K, pdot, u_in, act, x,
+    hipLaunchKernelGGL(cg_xr_kernel<64>, dim3((unsigned)rows), dim3(64), 0, s, N, K, pdot, u_in, act, x,
                        r, sv, t, ld, recompute_now, prr);
 }
 
 void launch_cg_s(int b, int64_t N, int K, const double *prr, const double *u_in, const int *act_in,
                  double *u_out, int *act_out, const double *u0, double eps2, int *iters,
-                 const double *r, double *sv, int64_t ld, hipStream_t s) {
+                 const double *r, double *sv, int64_t ld, hipStream_t s, int64_t rows) {
+  if (rows < 0 || rows > N) rows = N;
+  if (rows == 0) return;
   if (b == 128)
-    hipLaunchKernelGGL(cg_s_kernel<128>, dim3((unsigned)N), dim3(128), 0, s, N, K, prr, u_in, act_in,
+    hipLaunchKernelGGL(cg_s_kernel<128>, dim3((unsigned)rows), dim3(128), 0, s, N, K, prr, u_in, act_in,
                        u_out, act_out, u0, eps2, iters, r, sv, ld);
   else
-    hipLaunchKernelGGL(cg_s_kernel<64>, dim3((unsigned)N), dim3(64), 0, s, N, K, prr, u_in, act_in,
+    hipLaunchKernelGGL(cg_s_kernel<64>, dim3((unsigned)rows), dim3(64), 0, s, N, K, prr, u_in, act_in,
                        u_out, act_out, u0, eps2, iters, r, sv, ld);
 }
 

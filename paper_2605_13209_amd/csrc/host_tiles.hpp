@@ -35,3 +35,14 @@ int threads();
 
 }  // namespace host
 }  // namespace chol
+
+namespace chol {
+namespace host {
+// Both products of one lower tile T (column-major 128 x 128) in one pass:
+// y_row = T x_c (overwritten) and y_col += T^T x_i.  With `diag` (a
+// diagonal tile, strict upper part zero) y_row receives the full symmetric
+// product T x + T^T x - diag(T) x of x = x_c and y_col is not touched.
+void tile_symv_pair(const double *T, const double *x_c, const double *x_i, double *y_row,
+                    double *y_col, bool diag);
+}  // namespace host
+}  // namespace chol

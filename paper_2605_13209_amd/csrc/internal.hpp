@@ -132,21 +132,25 @@ void profile_end(hipStream_t s, hipEvent_t a, double work);
 
 // ---- conjugate gradients on the packed lower tiles (FP64) ----------------
 // Partial products of every stored tile with v (K columns, ldv): part holds
-// tile_count(N) * 2 * K * b doubles.
+// tile_count(N) * 2 * K * b doubles.  Nt >= 0: only the tiles of the leading
+// Nt block rows and columns (the heterogeneous CG's GPU share).
 void launch_cg_symv(const double *tiles, int b, int64_t N, const double *v, int64_t ldv, int K,
-                    double *part, hipStream_t s);
+                    double *part, hipStream_t s, int64_t Nt = -1);
 // Row sums of the partials; mode 0: t = A s and s.t partials, 1: r = b - A x
 // for active columns and r.r partials, 2: r = s = b - A x and r.r partials.
 enum { CG_RED_T = 0, CG_RED_RESID = 1, CG_RED_INIT = 2 };
+// Nt >= 0: block rows [0, Nt) only, from the tiles of the leading Nt block
+// rows and columns, plus `extra` (the other tiles' products for these rows).
 void launch_cg_reduce(const double *part, int b, int64_t N, int K, int mode, double *t, double *sv,
                       double *r, const double *bv, int64_t ld, const int *act, double *pdot,
-                      hipStream_t s);
+                      hipStream_t s, int64_t Nt = -1, const double *extra = nullptr);
+// rows >= 0: block rows [0, rows) only (the scalars still sum all N partials).
 void launch_cg_xr(int b, int64_t N, int K, const double *pdot, const double *u_in, const int *act,
                   double *x, double *r, const double *sv, const double *t, int64_t ld,
-                  int recompute_now, double *prr, hipStream_t s);
+                  int recompute_now, double *prr, hipStream_t s, int64_t rows = -1);
 void launch_cg_s(int b, int64_t N, int K, const double *prr, const double *u_in, const int *act_in,
                  double *u_out, int *act_out, const double *u0, double eps2, int *iters,
-                 const double *r, double *sv, int64_t ld, hipStream_t s);
+                 const double *r, double *sv, int64_t ld, hipStream_t s, int64_t rows = -1);
 void launch_cg_init(int b, int64_t N, int K, const double *prr, double *u, double *u0, int *act,
                     int *iters, double eps2, hipStream_t s);
 void launch_cg_copy_in(const double *src, int64_t lds, int64_t n, int64_t n_pad, int K, double *dst,
