@@ -263,6 +263,9 @@ def main():
     ap.add_argument("--rate", type=float, default=200.0, help="serve: mean arrivals per second")
     ap.add_argument("--workers", type=int, default=8, help="serve: concurrent requests")
     ap.add_argument("--oracle-sample", type=int, default=50, help="serve: requests checked against the oracle")
+    ap.add_argument("--serve-executor", default="batched", choices=["batched", "streams"],
+                    help="serve: continuous batching of the factorisations (one graph-captured column step "
+                         "for all active requests) or one stream and launch chain per request")
     ap.add_argument("--n", type=int, default=0, help="override the order")
     ap.add_argument("--tile", type=int, default=128)
     ap.add_argument("--panel-width", type=int, default=0)
@@ -894,14 +897,17 @@ def bench_serve(args):
     import torch
     import gp_inputs
     import oracle
-    from paper_2605_13209_amd.serve import HipExecutor, Server, SolveRequest
+    from paper_2605_13209_amd.serve import BatchedHipExecutor, HipExecutor, Server, SolveRequest
     stream = gp_inputs.serving_stream(duration_s=args.duration, rate=args.rate, seed=0)
 
     def to_req(r):
         return SolveRequest(X=r.features(), B=r.rhs(), lengthscale=r.lengthscale, variance=1.0,
                             noise=r.noise, key=r.key, rid=r.rid, tol=1e-10)
 
-    ex = HipExecutor(precision="fp32", method="ir", workers=args.workers)
+    if args.serve_executor == "batched":
+        ex = BatchedHipExecutor(method="ir", workers=args.workers)
+    else:
+        ex = HipExecutor(precision="fp32", method="ir", workers=args.workers)
     with Server(ex, hbm_budget=200e9, max_inflight=args.workers) as srv:  # warm-up, not timed
         for f in [srv.submit(to_req(r)) for r in gp_inputs.serving_stream(duration_s=0.1, seed=1)[:8]]:
             f.result()
@@ -920,6 +926,9 @@ def bench_serve(args):
     wall = time.perf_counter() - t0
     st = srv.stats()
     srv.close()
+    if args.serve_executor == "batched":
+        st["engine_steps"] = ex.steps
+        ex.close()
     offered = sum(r.n ** 3 / 3 + 4.0 * r.n * r.n * r.k for r in stream) / args.duration / 1e12
     achieved = st["gflops"] / 1e3 if st["gflops"] else 0.0
     out = {"metric": METRIC, "value": round(st["gflops"], 2), "unit": "GFLOP/s", "n_gpus": 1,
@@ -929,7 +938,8 @@ def bench_serve(args):
            "config": {"workload": "serve_poisson", "rate_per_s": args.rate, "duration_s": args.duration,
                       "n": "round(exp(U[ln 256, ln 8192]))", "rhs": "U{1..64}", "lengthscale": "U[0.3,2]",
                       "noise": "U[0.01,1]", "repeat_keys": 0.25, "precision": "fp32 factor + FP64 IR",
-                      "hbm_budget_gb": 200, "workers": args.workers, "seed": 0},
+                      "hbm_budget_gb": 200, "workers": args.workers, "seed": 0,
+                      "executor": args.serve_executor},
            # latency-bound: the delivered rate cannot exceed the offered load
            "roofline": {"bound": "mfma", "achieved": round(achieved, 4), "peak": FP32_PEAK_TFLOPS,
                         "unit": "TFLOP/s", "frac": round(achieved / FP32_PEAK_TFLOPS, 5), "traffic": None,

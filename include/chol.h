@@ -376,6 +376,50 @@ void chol_profile_reset(void);
 int chol_set_option(const char *key, int64_t value);
 int64_t chol_get_option(const char *key);
 
+/* ---- continuous-batching factorisation (the serving engine) ------------
+ * Many FP32 factorisations (tile 128) advance together, one tile column per
+ * step: a step is one batched diagonal-tile factorisation (Step 1, a
+ * workgroup per job), one batched panel solve (Step 2) and one batched
+ * trailing update (Step 3, FP32 matrix cores over a flat list of every
+ * job's trailing triangle), described by a device descriptor that the host
+ * rewrites before each step; with use_graph the three launches are captured
+ * once into a HIP graph and replayed.  Jobs join (chol_batch_add) and leave
+ * (when their last column is done) between steps, so requests that arrive
+ * while others are being factored share the next launches.  A job's tiles
+ * receive the same operations in the same order whatever else is in the
+ * batch: its factor is bitwise the same alone and in any mix.  The factor
+ * is that of chol_factor(..., CHOL_FP32, 128) computed column by column
+ * (panel width 1), so it is equal to it up to rounding, not bitwise.
+ * desc    : device memory, 256-byte aligned, >= chol_batch_desc_bytes(max_jobs),
+ *           owned by the caller and kept while the engine lives.
+ * stream  : the engine's stream (all its work, packing included, runs there;
+ *           required when use_graph is set).
+ * chol_batch_add: A (device, column-major FP64, lower read; it must be ready,
+ *   i.e. its producer synchronised, before the call) is packed into
+ *   workspace (>= chol_factor_bytes(n, CHOL_FP32, 128)) on the engine's
+ *   stream; *job receives the job's id.  CHOL_ERR_WORKSPACE when max_jobs
+ *   jobs are active.
+ * chol_batch_step: one step of every active job; *active = jobs in it,
+ *   *finished = jobs whose factorisation it completed.  Thread-safe with
+ *   chol_batch_add / status / take.
+ * chol_batch_status: *done = 1 once the job's last step is enqueued.
+ * chol_batch_take: the finished job's factor as a handle (free with
+ *   chol_factor_free); the job id is then released.  chol_get_info (and so
+ *   chol_refine_solve) waits for that job's kernels only, not the whole
+ *   engine stream; solves on other streams are ordered by that wait.
+ * Errors: CHOL_ERR_BAD_HANDLE, -i invalid argument i, CHOL_ERR_WORKSPACE,
+ *   CHOL_ERR_NOT_CONVERGED (take before the job finished), CHOL_ERR_HIP.   */
+typedef struct chol_batch_s *chol_batch;
+size_t chol_batch_desc_bytes(int max_jobs);
+int chol_batch_create(int max_jobs, void *desc, size_t desc_bytes, int use_graph,
+                      void *stream, chol_batch *out);
+void chol_batch_destroy(chol_batch b);
+int chol_batch_add(chol_batch b, const double *A, int64_t n, int64_t lda,
+                   void *workspace, size_t ws_bytes, int64_t *job);
+int chol_batch_step(chol_batch b, int *active, int *finished);
+int chol_batch_status(chol_batch b, int64_t job, int *done);
+int chol_batch_take(chol_batch b, int64_t job, chol_handle *F);
+
 /* ---- heterogeneous CPU + GPU factorisation ------------------------------
  * The paper's heterogeneous Cholesky (Implementation, "Cholesky
  * implementation"; Results, the heterogeneous Cholesky workload

@@ -13,4 +13,4 @@ from ._native import (CG_MAX_RHS, CgResult, cg_solve, cg_workspace_bytes,  # noq
                       chol_factor, chol_factor_bytes, chol_profile_read, chol_profile_reset, chol_factor_to_dense, chol_refine_bytes,
                       chol_refine_solve, chol_residual, chol_solve, chol_status_string, chol_tile_default,
                       colmajor_empty, get_option, gp_assemble, lib, set_option, to_colmajor,
-                      chol_factor_hetero, chol_hetero_host_bytes, cg_solve_hetero)
+                      chol_factor_hetero, chol_hetero_host_bytes, cg_solve_hetero, BatchEngine)

@@ -86,6 +86,13 @@ EXPORTS = {
     "cg_hetero_host_bytes": (_sz, [_i64, _dbl]),
     "cg_solve_hetero": (_int, [_vp, _i64, _i64, _vp, _vp, _dbl, _i64, _i64, _dbl, _vp, _sz, _vp, _sz,
                                ctypes.POINTER(_i64), ctypes.POINTER(_dbl), _vp, _vp]),
+    "chol_batch_desc_bytes": (_sz, [_int]),
+    "chol_batch_create": (_int, [_int, _vp, _sz, _int, _vp, ctypes.POINTER(_vp)]),
+    "chol_batch_destroy": (None, [_vp]),
+    "chol_batch_add": (_int, [_vp, _vp, _i64, _i64, _vp, _sz, ctypes.POINTER(_i64)]),
+    "chol_batch_step": (_int, [_vp, ctypes.POINTER(_int), ctypes.POINTER(_int)]),
+    "chol_batch_status": (_int, [_vp, _i64, ctypes.POINTER(_int)]),
+    "chol_batch_take": (_int, [_vp, _i64, ctypes.POINTER(_vp)]),
     "chol_host_potrf_tile": (_int, [_vp]),
     "chol_host_trsm_tile": (None, [_vp, _vp]),
     "chol_host_gemm_nt_tiles": (None, [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), _int, _int]),
@@ -346,6 +353,65 @@ def chol_refine_solve_noalloc(F: Factor, B: torch.Tensor, out: torch.Tensor, *, 
 
 def chol_refine_noalloc_max_bytes() -> int:
     return int(lib().chol_refine_noalloc_max_bytes())
+
+
+class BatchEngine:
+    """The continuous-batching factorisation engine (chol_batch_*): FP32
+    factors, tile 128, one tile column per step for every active job."""
+
+    def __init__(self, max_jobs: int = 64, stream=None, use_graph: bool = True, device=None):
+        self.max_jobs = int(max_jobs)
+        nb = int(lib().chol_batch_desc_bytes(self.max_jobs))
+        if nb == 0:
+            raise ValueError("max_jobs out of range")
+        dev = torch.device("cuda", torch.cuda.current_device()) if device is None else device
+        self.stream = stream if stream is not None else torch.cuda.Stream(device=dev)
+        self.desc = torch.empty(nb, dtype=torch.uint8, device=dev)
+        h = _vp()
+        _check(lib().chol_batch_create(self.max_jobs, self.desc.data_ptr(), nb, 1 if use_graph else 0,
+                                       _stream(self.stream), ctypes.byref(h)), "chol_batch_create")
+        self._h = h
+        self._ws = {}
+
+    def add(self, A: torch.Tensor, workspace: torch.Tensor | None = None) -> int:
+        _need_device(A, "A")
+        n = A.shape[0]
+        need = chol_factor_bytes(n, CHOL_FP32, 128)
+        if workspace is None:
+            workspace = torch.empty(need, dtype=torch.uint8, device=A.device)
+        job = _i64(0)
+        _check(lib().chol_batch_add(self._h, A.data_ptr(), n, _ld(A), workspace.data_ptr(),
+                                    workspace.numel() * workspace.element_size(), ctypes.byref(job)),
+               "chol_batch_add")
+        self._ws[int(job.value)] = workspace
+        return int(job.value)
+
+    def step(self) -> tuple[int, int]:
+        a, f = _int(0), _int(0)
+        _check(lib().chol_batch_step(self._h, ctypes.byref(a), ctypes.byref(f)), "chol_batch_step")
+        return int(a.value), int(f.value)
+
+    def done(self, job: int) -> bool:
+        d = _int(0)
+        _check(lib().chol_batch_status(self._h, int(job), ctypes.byref(d)), "chol_batch_status")
+        return bool(d.value)
+
+    def take(self, job: int) -> "Factor":
+        h = _vp()
+        _check(lib().chol_batch_take(self._h, int(job), ctypes.byref(h)), "chol_batch_take")
+        return Factor(h, self._ws.pop(int(job)), _stream(self.stream))
+
+    def close(self):
+        if self._h is not None:
+            torch.cuda.synchronize()
+            lib().chol_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class HeteroReport(ctypes.Structure):

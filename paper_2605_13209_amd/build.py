@@ -21,7 +21,7 @@ LIB = os.path.join(PKG, "libchol_mi355x.so")
 ARCH = os.environ.get("CHOL_OFFLOAD_ARCH", "gfx950")
 
 SOURCES = ["assemble.hip", "pack.hip", "potrf_trsm.hip", "update.hip", "trsv.hip", "blas1.hip",
-           "cg.hip", "chol_api.cpp", "cg_api.cpp", "hetero.cpp", "host_tiles.cpp", "cg_hetero.cpp"]
+           "cg.hip", "chol_api.cpp", "cg_api.cpp", "hetero.cpp", "host_tiles.cpp", "cg_hetero.cpp", "batch_api.cpp"]
 
 # Packed FP32 VALU instructions are disabled for every device pass.
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Wall", "-Wno-unused-function",

@@ -656,7 +656,10 @@ int chol_get_info(chol_handle F, int64_t *info) {
   if (!F) return CHOL_ERR_BAD_HANDLE;
   if (F->info < 0) {
     int64_t v = 0;
-    HIP_OK(hipStreamSynchronize(F->stream));
+    if (F->ev_ready)
+      HIP_OK(hipEventSynchronize(F->ev_ready));
+    else
+      HIP_OK(hipStreamSynchronize(F->stream));
     HIP_OK(hipMemcpy(&v, F->d_info, sizeof(int64_t), hipMemcpyDeviceToHost));
     F->info = v;
   }

@@ -40,8 +40,13 @@ struct chol_factor_s {
   hipEvent_t ev_solve = nullptr;
   hipStream_t last_solve = nullptr;
   bool solved = false;
+  // Set by the batched engine: recorded after the factor's last kernel on a
+  // stream shared with other work; chol_get_info waits for it instead of
+  // the whole stream.
+  hipEvent_t ev_ready = nullptr;
   ~chol_factor_s() {
     if (ev_solve) (void)hipEventDestroy(ev_solve);
+    if (ev_ready) (void)hipEventDestroy(ev_ready);
   }
 };
 

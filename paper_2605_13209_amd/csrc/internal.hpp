@@ -27,6 +27,31 @@ __host__ __device__ inline int64_t tile_count(int64_t N) { return N * (N + 1) / 
 // Element storage kinds of the factor.
 enum Store : int { STORE_F64 = 0, STORE_F32 = 1 };
 
+// Descriptor of one batched column step (the serving engine): job j is at
+// tile column c of its own packed FP32 matrix (tile 128); its panel solves
+// are entries [trsm_begin, trsm_begin + N - c - 1) of the step's flat list,
+// its trailing-triangle updates entries [upd_begin, upd_begin + R (R + 1) / 2),
+// R = N - c - 1.  Jobs are ordered by both prefixes.
+struct BatchJob {
+  void *tiles;
+  int64_t *info;
+  int64_t N, c, trsm_begin, upd_begin;
+  int64_t pad[2];
+};
+struct BatchDesc {
+  int64_t njobs, trsm_total, upd_total;
+  int64_t pad[5];
+  BatchJob jobs[1];  // njobs entries
+};
+constexpr size_t batch_desc_bytes(int max_jobs) {
+  return sizeof(BatchDesc) + (size_t)(max_jobs > 1 ? max_jobs - 1 : 0) * sizeof(BatchJob);
+}
+// One batched column step: the diagonal tiles (one workgroup per job, grid
+// max_jobs), then the panel solves (grid trsm_grid, walking the flat list),
+// then the trailing updates (persistent grid upd_grid, FP32 matrix cores).
+void launch_batch_potrf_trsm(const BatchDesc *d, int max_jobs, int trsm_grid, hipStream_t s);
+void launch_batch_update(const BatchDesc *d, int upd_grid, int super_tile, hipStream_t s);
+
 // ---- launchers (all asynchronous on `s`) --------------------------------
 // gp_assemble into a column-major matrix.
 void launch_gp_assemble(const double *X, int64_t n, int64_t d, int64_t ldx, double two_l2,

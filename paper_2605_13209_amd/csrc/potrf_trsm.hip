@@ -77,8 +77,8 @@ __device__ __forceinline__ void row_solve(double (&x)[NB], const double *l, cons
 // (contiguous global reads).  256 threads, LDS below 36 KB: the kernel fits
 // on a CU beside one trailing-update workgroup.
 template <int B, typename T>
-__global__ __launch_bounds__(256) void potrf_kernel(T *__restrict__ tiles, int64_t N, int64_t c,
-                                                    int64_t *__restrict__ info) {
+__device__ __forceinline__ void potrf_body(T *__restrict__ tiles, int64_t N, int64_t c,
+                                           int64_t *__restrict__ info) {
   if (*info != 0) return;
   constexpr int M = B / 16;
   constexpr int NB = 16;
@@ -226,6 +226,12 @@ __global__ __launch_bounds__(256) void potrf_kernel(T *__restrict__ tiles, int64
 #pragma unroll
       for (int n = 0; n + 1 < M; ++n) a[m][n] = a[m + 1][n + 1];
   }
+}
+
+template <int B, typename T>
+__global__ __launch_bounds__(256) void potrf_kernel(T *__restrict__ tiles, int64_t N, int64_t c,
+                                                    int64_t *__restrict__ info) {
+  potrf_body<B, T>(tiles, N, c, info);
 }
 
 // ---------------------------------------------------------------- Step 2 --
@@ -391,6 +397,34 @@ __global__ __launch_bounds__(256) void diag_inverse_kernel(const T *__restrict__
                         dinv + c * (int64_t)(B * B));
 }
 
+// Batched column step of several factorisations at once (the serving
+// engine): job j of the descriptor is at tile column c_j of its own packed
+// matrix.  One workgroup per job factors its diagonal tile; the panel solves
+// of all jobs form one flat list that a fixed grid walks.
+template <int B, typename T>
+__global__ __launch_bounds__(256) void batch_potrf_kernel(const BatchDesc *__restrict__ d) {
+  const int64_t j = blockIdx.x;
+  if (j >= d->njobs) return;
+  const BatchJob &J = d->jobs[j];
+  potrf_body<B, T>((T *)J.tiles, J.N, J.c, J.info);
+}
+
+template <int B, typename T>
+__global__ __launch_bounds__(256) void batch_trsm_kernel(const BatchDesc *__restrict__ d) {
+  const int64_t total = d->trsm_total, nj = d->njobs;
+  for (int64_t t = blockIdx.x; t < total; t += gridDim.x) {
+    int64_t j = 0;
+    while (j + 1 < nj && d->jobs[j + 1].trsm_begin <= t) ++j;
+    const BatchJob &J = d->jobs[j];
+    if (*J.info != 0) continue;  // uniform over the workgroup
+    T *tiles = (T *)J.tiles;
+    const int64_t i = J.c + 1 + (t - J.trsm_begin);
+    trsm_tile<B, T, false>(tiles + tile_index(J.c, J.c, J.N) * (int64_t)(B * B),
+                           tiles + tile_index(i, J.c, J.N) * (int64_t)(B * B));
+    __syncthreads();  // the tile's LDS is reused by the next one
+  }
+}
+
 template <int B>
 void potrf_dispatch(void *tiles, int store, int64_t N, int64_t c, int64_t *info, hipStream_t s) {
   if (store == STORE_F64)
@@ -445,6 +479,11 @@ void launch_diag_inverse(const void *tiles, int store, int b, int64_t N, void *d
       hipLaunchKernelGGL((diag_inverse_kernel<64, float>), grid, dim3(256), 0, s,
                          (const float *)tiles, N, (float *)dinv, info);
   }
+}
+
+void launch_batch_potrf_trsm(const BatchDesc *d, int max_jobs, int trsm_grid, hipStream_t s) {
+  hipLaunchKernelGGL((batch_potrf_kernel<128, float>), dim3((unsigned)max_jobs), dim3(256), 0, s, d);
+  hipLaunchKernelGGL((batch_trsm_kernel<128, float>), dim3((unsigned)trsm_grid), dim3(256), 0, s, d);
 }
 
 void launch_trsm(void *tiles, int store, int b, int64_t N, int64_t c, const int64_t *info,

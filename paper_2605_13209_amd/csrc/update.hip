@@ -72,13 +72,22 @@ __device__ inline void wait_vmem() { asm volatile("s_waitcnt vmcnt(0)" ::: "memo
 // conflict-free without padding), two chunks ahead, with the same one-barrier
 // protocol as the FP64 kernel below (barrier after the second-to-last k-step
 // of a chunk).
+// REGION 3 (the serving engine's batched column step): the work list of a
+// BatchDesc (passed as `tiles`), whose job j contributes the trailing
+// triangle of its column c_j (panel width 1); G and G8 are read from it.
 template <int REGION>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void update_f32_kernel(
     float *__restrict__ tiles, int64_t N, int64_t p0, int pw, int64_t k0, int64_t K, int S,
     int64_t G, int64_t G8, const int64_t *__restrict__ info) {
   constexpr int KC = 32;        // panel columns per chunk
   constexpr int NKS = KC / 4;   // k-steps per chunk
-  if (*info != 0) return;
+  const BatchDesc *bd = (const BatchDesc *)tiles;
+  if (REGION == 3) {
+    G = bd->upd_total;
+    G8 = (G + 7) / 8;
+  } else if (*info != 0) {
+    return;
+  }
   __shared__ __attribute__((aligned(16))) float lds[2][2][KC * BT];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int g = lane >> 4, q = lane & 15;
@@ -88,22 +97,40 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void u
   for (int64_t pos = blockIdx.x / 8; pos < G8; pos += per) {
     const int64_t t = (blockIdx.x % 8) * G8 + pos;
     if (t >= G) break;
-    int64_t ir, kr;
-    if (REGION == 0)
-      map_triangle(t, N - k0, S, ir, kr);
-    else
-      map_band(t, K, ir, kr);
-    const int64_t i = k0 + ir, k = k0 + kr;
-    float *C = tiles + tile_index(i, k, N) * (int64_t)(BT * BT);
+    float *tl = tiles;
+    int64_t NN = N, P0 = p0, i, k;
+    if (REGION == 3) {
+      int64_t j = 0;
+      const int64_t nj = bd->njobs;
+      while (j + 1 < nj && bd->jobs[j + 1].upd_begin <= t) ++j;
+      const BatchJob &J = bd->jobs[j];
+      if (*J.info != 0) continue;  // uniform over the workgroup
+      int64_t ir, kr;
+      map_triangle(t - J.upd_begin, J.N - J.c - 1, S, ir, kr);
+      tl = (float *)J.tiles;
+      NN = J.N;
+      P0 = J.c;
+      i = J.c + 1 + ir;
+      k = J.c + 1 + kr;
+    } else {
+      int64_t ir, kr;
+      if (REGION == 0)
+        map_triangle(t, N - k0, S, ir, kr);
+      else
+        map_band(t, K, ir, kr);
+      i = k0 + ir;
+      k = k0 + kr;
+    }
+    float *C = tl + tile_index(i, k, NN) * (int64_t)(BT * BT);
     const int nstage = pw * (BT / KC);
 
     // chunk s: 32 columns = 16 KB per operand = 16 one-KB column pairs;
     // wave w moves pairs w, w+4, w+8, w+12 of both operands
     auto dma = [&](int s) {
-      const int64_t p = p0 + (s * KC) / BT;
+      const int64_t p = P0 + (s * KC) / BT;
       const int col0 = (s * KC) % BT;
-      const float *pa = tiles + tile_index(i, p, N) * (int64_t)(BT * BT) + col0 * BT;
-      const float *pb = tiles + tile_index(k, p, N) * (int64_t)(BT * BT) + col0 * BT;
+      const float *pa = tl + tile_index(i, p, NN) * (int64_t)(BT * BT) + col0 * BT;
+      const float *pb = tl + tile_index(k, p, NN) * (int64_t)(BT * BT) + col0 * BT;
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
         const int off = (wu + 4 * c) * 2 * BT;
@@ -725,6 +752,12 @@ void launch_update(void *tiles, int store, int b, int64_t N, int64_t p0, int pw,
       hipLaunchKernelGGL(update64_kernel<float>, grid, dim3(256), 0, s, (float *)tiles, N, p0, pw,
                          k0, K, mode, super_tile, G, info);
   }
+}
+
+void launch_batch_update(const BatchDesc *d, int upd_grid, int super_tile, hipStream_t s) {
+  hipLaunchKernelGGL(update_f32_kernel<3>, dim3((unsigned)(upd_grid / 8 * 8)), dim3(256), 0, s,
+                     (float *)d, (int64_t)0, (int64_t)0, 1, (int64_t)0, (int64_t)0, super_tile,
+                     (int64_t)0, (int64_t)0, (const int64_t *)nullptr);
 }
 
 void launch_panel_f16(const void *tiles, int64_t N, int64_t c0, int pw, void *p16,

@@ -35,8 +35,8 @@ from typing import Any, Hashable, Optional
 
 import numpy as np
 
-__all__ = ["SolveRequest", "SolveResult", "Executor", "HipExecutor", "Server", "TuningTable",
-           "RequestTooLarge"]
+__all__ = ["SolveRequest", "SolveResult", "Executor", "HipExecutor", "BatchedHipExecutor", "EngineStepper",
+           "Server", "TuningTable", "RequestTooLarge"]
 
 
 class RequestTooLarge(RuntimeError):
@@ -164,6 +164,137 @@ class HipExecutor(Executor):
                                  device=self.device)
                 F = P.chol_factor(A, self.precision, tile, workspace=ws, sync=False, stream=stream,
                                   panel_width=width)
+                entry = {"A": A, "X": Xd, "ws": ws, "F": F}
+                reused = False
+            else:
+                entry, reused = cached, True
+            Bh = np.asfortranarray(req.B.reshape(n, -1), dtype=np.float64)
+            Bd = P.to_colmajor(torch.from_numpy(Bh).pin_memory(), device=self.device)
+            res = P.chol_refine_solve(entry["F"], Bd, A=entry["A"], noise=req.noise, tol=req.tol,
+                                      method=self.method, max_iter=self.max_iter, raise_on_fail=False,
+                                      stream=stream)
+            Xh = res.X.to("cpu", non_blocking=False).numpy()
+        flops = (0 if reused else n ** 3 / 3) + 4.0 * n * n * req.k * (1 + res.iters)
+        return (SolveResult(Xh, res.iters, res.converged, res.cert, reused, req.t_arrival, t_admit,
+                            time.perf_counter(), flops), entry)
+
+
+class EngineStepper:
+    """Drives a batching engine (step() -> (active, finished), done(job)):
+    a thread runs steps while jobs are pending; wait(job) returns once the
+    job's last step is enqueued.  An exception in the stepping thread is
+    kept and raised in every waiter (and later submitter) instead of leaving
+    them waiting; wait() also gives up after `timeout` seconds."""
+
+    def __init__(self, engine, on_thread_start=None, timeout: float = 600.0):
+        self.engine = engine
+        self.timeout = timeout
+        self._cv = threading.Condition()
+        self._pending = 0
+        self._closing = False
+        self._error: Optional[BaseException] = None
+        self.steps = 0
+        self._on_start = on_thread_start
+        self._thread = threading.Thread(target=self._run, name="gp-batch-steps", daemon=True)
+        self._thread.start()
+
+    def _run(self):
+        try:
+            if self._on_start:
+                self._on_start()
+            while True:
+                with self._cv:
+                    while self._pending == 0 and not self._closing:
+                        self._cv.wait()
+                    if self._closing:
+                        return
+                active, finished = self.engine.step()
+                with self._cv:
+                    self.steps += 1
+                    if finished:
+                        self._pending -= finished
+                        self._cv.notify_all()
+        except BaseException as e:  # noqa: BLE001 - handed to the waiters
+            with self._cv:
+                self._error = e
+                self._cv.notify_all()
+
+    def submit(self, add):
+        """Run add() (which registers a job with the engine) and count it."""
+        with self._cv:
+            if self._error is not None:
+                raise RuntimeError("batching engine stopped") from self._error
+            job = add()
+            self._pending += 1
+            self._cv.notify_all()
+            return job
+
+    def wait(self, job):
+        deadline = time.monotonic() + self.timeout
+        with self._cv:
+            while not self.engine.done(job):
+                if self._error is not None:
+                    raise RuntimeError("batching engine stopped") from self._error
+                left = deadline - time.monotonic()
+                if left <= 0:
+                    raise TimeoutError(f"job {job} not finished after {self.timeout} s "
+                                       f"({self.steps} steps, {self._pending} pending)")
+                self._cv.wait(timeout=min(left, 1.0))
+
+    def close(self):
+        """Stop stepping (jobs still pending are left unfinished)."""
+        with self._cv:
+            self._closing = True
+            self._cv.notify_all()
+        self._thread.join()
+
+
+class BatchedHipExecutor(HipExecutor):
+    """The GPU backend with continuous batching of the factorisations: every
+    admitted request's FP32 factorisation (tile 128) joins the library's
+    batching engine (chol_batch_*), whose steps advance all active requests
+    by one tile column with one batched diagonal-tile factorisation, panel
+    solve and trailing update, captured once in a HIP graph and replayed.
+    A stepping thread runs steps while jobs are active; the request's worker
+    thread assembles A on its own stream, hands it to the engine, waits for
+    its last step and runs the FP64 refinement on its own stream."""
+
+    def __init__(self, method: str = "ir", device: int = 0, workers: int = 8, max_iter: int = 30,
+                 max_jobs: int = 64, use_graph: bool = True):
+        super().__init__(precision="fp32", method=method, device=device, workers=workers, max_iter=max_iter)
+        P = self.P
+        self.engine_stream = self.torch.cuda.Stream(device=self.device)
+        self.engine = P.BatchEngine(max_jobs=max_jobs, stream=self.engine_stream, use_graph=use_graph,
+                                    device=self.device)
+        self.stepper = EngineStepper(self.engine, on_thread_start=lambda: self.torch.cuda.set_device(self.device))
+
+    @property
+    def steps(self) -> int:
+        return self.stepper.steps
+
+    def _tile(self, n: int) -> tuple[int, int]:
+        return 128, 1
+
+    def close(self):
+        self.stepper.close()
+        self.engine.close()
+
+    def run(self, req, cached, worker):
+        torch, P = self.torch, self.P
+        stream = self.streams[worker % len(self.streams)]
+        n = req.n
+        t_admit = time.perf_counter()
+        with torch.cuda.stream(stream):
+            if cached is None:
+                Xd = torch.from_numpy(np.ascontiguousarray(req.X, dtype=np.float64)).pin_memory().to(
+                    self.device, non_blocking=True)
+                A = P.colmajor_empty(n, n, device=self.device)
+                P.gp_assemble(Xd, req.lengthscale, req.variance, req.noise, full=False, out=A, stream=stream)
+                ws = torch.empty(P.chol_factor_bytes(n, "fp32", 128), dtype=torch.uint8, device=self.device)
+                stream.synchronize()  # A ready before the engine's stream packs it
+                job = self.stepper.submit(lambda: self.engine.add(A, ws))
+                self.stepper.wait(job)
+                F = self.engine.take(job)
                 entry = {"A": A, "X": Xd, "ws": ws, "F": F}
                 reused = False
             else:
