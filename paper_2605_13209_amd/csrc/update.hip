@@ -15,8 +15,9 @@
 //   the panel operands are used unmodified and each MFMA adds a b^T.
 // * Rows are interleaved across the MFMA blocks of a wave so that a lane's
 //   A (or B) fragments come from 16-byte LDS reads that are contiguous
-//   across lanes, and a lane's accumulators form 16-byte runs of C columns
-//   (vector loads/stores of C straight to and from HBM).
+//   across lanes, and a lane's accumulators form runs of C columns moved
+//   with vector loads/stores straight to and from HBM (FP32 C: exchanged
+//   between lanes first, so that every access covers whole 64-byte pieces).
 // * FP64 / FP32: the panel is streamed through LDS in chunks of 128 bytes per
 //   tile row by LDS DMA (global_load_lds_dwordx4), two chunks ahead, and the
 //   fragments of the next k-step are read while the MFMAs of the current one
@@ -59,6 +60,51 @@ __device__ inline void lds_dma16(const void *base, uint32_t voff, void *lds_dst)
 }
 __device__ inline void wait_vmem() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
 
+// C runs of the FP32-accumulating kernels.  In the MFMA output layout lane
+// (g, q) of a wave holds, for one output column, the 16 rows 16 g + 4 e + s2
+// of a 64-row block (register e, component s2): 64 contiguous bytes per lane.
+// Moved as is, one 16-byte access per e would touch four 16-byte pieces 64
+// bytes apart per column, and partly written lines leave L2 as partial
+// writes (counted: 1.45x the C bytes).  Instead the four lanes g = 0..3 of a
+// column exchange their registers as a 4 x 4 transpose (two lane-swap
+// stages: rows of 32 lanes, then rows of 16), after which access e of the
+// four lanes covers the 64 contiguous bytes of rows 16 e .. 16 e + 15.  The
+// transpose is its own inverse, so loads apply it after, stores before.
+__device__ inline void xpose_g(v4f *x) {
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      const auto t = __builtin_amdgcn_permlane32_swap(__float_as_uint(x[e][c]),
+                                                      __float_as_uint(x[e + 2][c]), false, false);
+      x[e][c] = __uint_as_float(t[0]);
+      x[e + 2][c] = __uint_as_float(t[1]);
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+#pragma unroll
+    for (int e = 0; e < 4; e += 2) {
+      const auto t = __builtin_amdgcn_permlane16_swap(__float_as_uint(x[e][c]),
+                                                      __float_as_uint(x[e + 1][c]), false, false);
+      x[e][c] = __uint_as_float(t[0]);
+      x[e + 1][c] = __uint_as_float(t[1]);
+    }
+  }
+}
+// c: the 64-row block of the lane's column; x[e][s2] = row 16 g + 4 e + s2.
+// Every lane of the wave must take part (cross-lane exchange).
+__device__ inline void load_c_run(const float *c, int g, v4f *x) {
+#pragma unroll
+  for (int e = 0; e < 4; ++e) x[e] = *(const v4f *)(c + 16 * e + 4 * g);
+  xpose_g(x);
+}
+__device__ inline void store_c_run(float *c, int g, v4f *x) {
+  xpose_g(x);
+#pragma unroll
+  for (int e = 0; e < 4; ++e) *(v4f *)(c + 16 * e + 4 * g) = x[e];
+}
+
 // ------------------------------------------------------------------ FP32 --
 // FP32 storage and arithmetic on v_mfma_f32_16x16x4_f32.  Each wave owns a
 // 64 x 64 block as 4 x 4 MFMA blocks (s2, u).  MFMA row i of block s2 is
@@ -67,7 +113,7 @@ __device__ inline void wait_vmem() { asm volatile("s_waitcnt vmcnt(0)" ::: "memo
 // 16-byte LDS read each, contiguous across lanes.  With the MFMA output
 // layout (lane (g, q), register e holds MFMA row 4g + e, column q) the
 // accumulator acc[s2][u][e] is C(64 wm + 16g + 4e + s2, 64 wn + 4q + u):
-// C moves as 16-byte vectors.  Chunks of 32 panel columns (128 bytes per tile
+// C moves as 16-byte vectors, through load_c_run / store_c_run.  Chunks of 32 panel columns (128 bytes per tile
 // row) are DMA'd into unpadded LDS (the 16-byte fragment reads are
 // conflict-free without padding), two chunks ahead, with the same one-barrier
 // protocol as the FP64 kernel below (barrier after the second-to-last k-step
@@ -142,14 +188,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void u
     v4f acc[4][4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      const float *col = C + (64 * wn + 4 * q + u) * BT + 64 * wm + 16 * g;
+      v4f x[4];
+      load_c_run(C + (64 * wn + 4 * q + u) * BT + 64 * wm, g, x);
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        float v[4];
-        *(uint4 *)&v[0] = *(const uint4 *)(col + 4 * e);
+      for (int e = 0; e < 4; ++e)
 #pragma unroll
-        for (int s2 = 0; s2 < 4; ++s2) acc[s2][u][e] = -v[s2];
-      }
+        for (int s2 = 0; s2 < 4; ++s2) acc[s2][u][e] = -x[e][s2];
     }
     dma(0);
     if (nstage > 1) dma(1);
@@ -187,14 +231,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void u
 
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      float *col = C + (64 * wn + 4 * q + u) * BT + 64 * wm + 16 * g;
+      v4f x[4];
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        float v[4];
+      for (int e = 0; e < 4; ++e)
 #pragma unroll
-        for (int s2 = 0; s2 < 4; ++s2) v[s2] = -acc[s2][u][e];
-        *(uint4 *)(col + 4 * e) = *(const uint4 *)&v[0];
-      }
+        for (int s2 = 0; s2 < 4; ++s2) x[e][s2] = -acc[s2][u][e];
+      store_c_run(C + (64 * wn + 4 * q + u) * BT + 64 * wm, g, x);
     }
   }  // tiles of this workgroup
 }
@@ -370,6 +412,20 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void u
 constexpr int P16_CHMAX = 32;  // chunks of 64 columns per tile row (panel width <= 16)
 constexpr int P16_CHUNK = BT * 64;  // halves per chunk
 
+// Position (in halves) of row r, 16-byte segment sg of a converted chunk.
+// A fragment read has the 16 lanes of one lane group on rows 4q + s2
+// (q = 0..15) of one operand.  Segments are XOR-swizzled by q mod 8, and the
+// stored row takes bit 5 of the logical row (the high bit of q) as its bit 0,
+// so the sixteen lanes cover both 128-byte halves of a 256-byte line of all
+// 64 LDS banks with distinct segments: one 128-bit read is conflict-free.
+// The low two row bits (s2) move to bits 4-5 so that the four rows a lane
+// reads differ by constant offsets.  The update kernels DMA chunks verbatim,
+// so the LDS layout equals this one.
+__device__ __forceinline__ int p16_pos(int r, int sg) {
+  const int pr = (r & 64) | ((r & 3) << 4) | (((r >> 2) & 7) << 1) | ((r >> 5) & 1);
+  return pr * 64 + 8 * (sg ^ ((r >> 2) & 7));
+}
+
 __global__ __launch_bounds__(256) void panel_f16_kernel(const float *__restrict__ tiles, int64_t N,
                                                         int64_t c0, _Float16 *__restrict__ p16,
                                                         const int64_t *__restrict__ info) {
@@ -394,7 +450,7 @@ __global__ __launch_bounds__(256) void panel_f16_kernel(const float *__restrict_
     v8h v;
 #pragma unroll
     for (int j = 0; j < 8; ++j) v[j] = (_Float16)st[(8 * sg + j) * PAD + r];
-    *(v8h *)(dst + r * 64 + 8 * (sg ^ ((r >> 2) & 7))) = v;
+    *(v8h *)(dst + p16_pos(r, sg)) = v;
   }
 }
 
@@ -439,14 +495,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void u
     v4f acc[4][4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      const float *col = C + (64 * wn + 4 * q + u) * BT + 64 * wm + 16 * g;
+      v4f x[4];
+      load_c_run(C + (64 * wn + 4 * q + u) * BT + 64 * wm, g, x);
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        float v[4];
-        *(uint4 *)&v[0] = *(const uint4 *)(col + 4 * e);
+      for (int e = 0; e < 4; ++e)
 #pragma unroll
-        for (int s2 = 0; s2 < 4; ++s2) acc[s2][u][e] = -v[s2];
-      }
+        for (int s2 = 0; s2 < 4; ++s2) acc[s2][u][e] = -x[e][s2];
     }
     dma(0);
     if (nstage > 1) dma(1);
@@ -454,9 +508,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void u
     __syncthreads();
     // fragment of wave-local row 4q + s2 (operand base row r0), k-step ks
     auto frag = [&](const _Float16 *l, int r0, int s2, int ks) -> v8h {
-      const int r = r0 + 4 * q + s2;
-      const int sg = (4 * ks + g) ^ ((r >> 2) & 7);
-      return *(const v8h *)(l + r * 64 + 8 * sg);
+      return *(const v8h *)(l + p16_pos(r0 + 4 * q + s2, 4 * ks + g));
     };
     v8h fa[2][4], fb[2][4];
 #pragma unroll
@@ -494,14 +546,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void u
     }
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      float *col = C + (64 * wn + 4 * q + u) * BT + 64 * wm + 16 * g;
+      v4f x[4];
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        float v[4];
+      for (int e = 0; e < 4; ++e)
 #pragma unroll
-        for (int s2 = 0; s2 < 4; ++s2) v[s2] = -acc[s2][u][e];
-        *(uint4 *)(col + 4 * e) = *(const uint4 *)&v[0];
-      }
+        for (int s2 = 0; s2 < 4; ++s2) x[e][s2] = -acc[s2][u][e];
+      store_c_run(C + (64 * wn + 4 * q + u) * BT + 64 * wm, g, x);
     }
   }  // tiles of this workgroup
 }
@@ -555,14 +605,12 @@ __global__ __launch_bounds__(512) void update_f16_wide_kernel(
       for (int h = 0; h < 2; ++h)
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-          const float *col = C + (cb + 4 * q + u) * BT + 64 * h + 16 * g;
+          v4f x[4];
+          load_c_run(C + (cb + 4 * q + u) * BT + 64 * h, g, x);
 #pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            float v[4];
-            *(uint4 *)&v[0] = *(const uint4 *)(col + 4 * e);
+          for (int e = 0; e < 4; ++e)
 #pragma unroll
-            for (int s2 = 0; s2 < 4; ++s2) acc[h][s2][u][e] = -v[s2];
-          }
+            for (int s2 = 0; s2 < 4; ++s2) acc[h][s2][u][e] = -x[e][s2];
         }
     } else {
 #pragma unroll
@@ -577,9 +625,7 @@ __global__ __launch_bounds__(512) void update_f16_wide_kernel(
     wait_vmem();
     __syncthreads();
     auto frag = [&](const _Float16 *l, int r0, int s2, int ks) -> v8h {
-      const int r = r0 + 4 * q + s2;
-      const int sg = (4 * ks + g) ^ ((r >> 2) & 7);
-      return *(const v8h *)(l + r * 64 + 8 * sg);
+      return *(const v8h *)(l + p16_pos(r0 + 4 * q + s2, 4 * ks + g));
     };
     v8h fa[2][8], fb[2][4];
 #pragma unroll
@@ -621,14 +667,12 @@ __global__ __launch_bounds__(512) void update_f16_wide_kernel(
       for (int h = 0; h < 2; ++h)
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-          float *col = C + (cb + 4 * q + u) * BT + 64 * h + 16 * g;
+          v4f x[4];
 #pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            float v[4];
+          for (int e = 0; e < 4; ++e)
 #pragma unroll
-            for (int s2 = 0; s2 < 4; ++s2) v[s2] = -acc[h][s2][u][e];
-            *(uint4 *)(col + 4 * e) = *(const uint4 *)&v[0];
-          }
+            for (int s2 = 0; s2 < 4; ++s2) x[e][s2] = -acc[h][s2][u][e];
+          store_c_run(C + (cb + 4 * q + u) * BT + 64 * h, g, x);
         }
     }
     __syncthreads();  // every wave's last LDS read before the next super-tile's DMA
