@@ -34,6 +34,7 @@ namespace chol {
 namespace {
 
 typedef float v4f __attribute__((ext_vector_type(4)));
+typedef unsigned v4u __attribute__((ext_vector_type(4)));
 typedef _Float16 v8h __attribute__((ext_vector_type(8)));
 
 constexpr int BT = 128;  // tile side handled by the matrix-core kernels
@@ -679,51 +680,144 @@ __global__ __launch_bounds__(512) void update_f16_wide_kernel(
   }  // super-tiles of this workgroup
 }
 
-// Portable fallback for tile side 64 (small problems): one workgroup of 256
-// threads per 64 x 64 tile, plain FP64 FMAs, panel read through LDS.
+// Tile side 64 (small problems), on the matrix cores: one wave per 64 x 64
+// output tile, four independent waves per workgroup (tile 4 w + wave), so a
+// wave's whole 64 x 64 block is the tile and no workgroup barrier is needed.
+// Each wave stages its own two panel slices through its own LDS (global
+// loads, then LDS writes, then the fragment reads of the chunk), one chunk
+// of KC panel columns at a time.
+//   FP64 storage: v_mfma_f64_4x4x4_4b_f64 with the lane layout of the
+//     128-tile FP64 kernel (acc[x][y] = -C(8 bq + 2g + (x&1) + 32(x>>1),
+//     4y + jq)); chunks of 16 columns, LDS column pitch 68 doubles.
+//   FP32 storage: v_mfma_f32_16x16x4_f32 with the layout of the 128-tile
+//     FP32 kernel (acc[s2][u][e] = -C(16g + 4e + s2, 4q + u)), FP32
+//     accumulation; chunks of 32 columns, unpadded LDS.
+// The panel columns enter the accumulators in increasing order, so splitting
+// a panel over several launches gives the bitwise same tile.
 template <typename T>
 __global__ __launch_bounds__(256) void update64_kernel(T *__restrict__ tiles, int64_t N,
                                                        int64_t p0, int pw, int64_t k0, int64_t K,
                                                        int mode, int S, int64_t G,
                                                        const int64_t *__restrict__ info) {
   constexpr int B = 64;
+  constexpr bool F64 = sizeof(T) == 8;
+  constexpr int KC = F64 ? 16 : 32;     // panel columns per chunk (8 KB per operand)
+  constexpr int LDP = F64 ? B + 4 : B;  // LDS column pitch (elements)
   if (*info != 0) return;
-  const int64_t t = blockIdx.x;
-  if (t >= G) return;
+  __shared__ __attribute__((aligned(16))) T lds[4][2][KC * LDP];
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int64_t t = 4 * (int64_t)blockIdx.x + wv;
+  if (t >= G) return;  // the whole wave
   int64_t ir, kr;
   if (mode == 0)
     map_triangle(t, N - k0, S, ir, kr);
   else
     map_band(t, K, ir, kr);
   const int64_t i = k0 + ir, k = k0 + kr;
-  __shared__ double la[16][B + 1], lb[16][B + 1];
   T *C = tiles + tile_index(i, k, N) * (int64_t)(B * B);
-  const int tid = threadIdx.x;
-  const int r = tid & 63, cg = tid >> 6;  // row r, columns cg + 4m
-  double acc[16];
+  T *la = lds[wv][0], *lb = lds[wv][1];
+  const int g = lane >> 4, q = lane & 15;
+  const int nch = pw * (B / KC);
+  // chunk s: columns [KC s mod 64, +KC) of panel tile p0 + KC s / 64; lane
+  // moves eight 16-byte pieces of each operand (column e / (64 / VE), rows
+  // VE (e mod (64 / VE)) .. +VE-1 for piece e = 64 c + lane)
+  auto stage = [&](int s) {
+    constexpr int VE = 16 / sizeof(T), PPC = B / VE;  // elements per piece, pieces per column
+    const int64_t p = p0 + (s * KC) / B;
+    const int col0 = (s * KC) % B;
+    const T *pa = tiles + tile_index(i, p, N) * (int64_t)(B * B) + col0 * B;
+    const T *pb = tiles + tile_index(k, p, N) * (int64_t)(B * B) + col0 * B;
+    v4u va[8], vb[8];
 #pragma unroll
-  for (int m = 0; m < 16; ++m) acc[m] = (double)C[(cg + 4 * m) * B + r];
-  for (int p = 0; p < pw; ++p) {
-    const T *pa = tiles + tile_index(i, p0 + p, N) * (int64_t)(B * B);
-    const T *pb = tiles + tile_index(k, p0 + p, N) * (int64_t)(B * B);
-    for (int kc = 0; kc < B; kc += 16) {
-      __syncthreads();
-      for (int e = tid; e < 16 * B; e += 256) {
-        const int kk = e / B, rr = e % B;
-        la[kk][rr] = (double)pa[(kc + kk) * B + rr];
-        lb[kk][rr] = (double)pb[(kc + kk) * B + rr];
-      }
-      __syncthreads();
+    for (int c = 0; c < 8; ++c) {
+      const int e = 64 * c + lane, col = e / PPC, row = VE * (e % PPC);
+      va[c] = *(const v4u *)(pa + col * B + row);
+      vb[c] = *(const v4u *)(pb + col * B + row);
+    }
 #pragma unroll
-      for (int kk = 0; kk < 16; ++kk) {
-        const double av = la[kk][r];
+    for (int c = 0; c < 8; ++c) {
+      const int e = 64 * c + lane, col = e / PPC, row = VE * (e % PPC);
+      *(v4u *)(la + col * LDP + row) = va[c];
+      *(v4u *)(lb + col * LDP + row) = vb[c];
+    }
+  };
+  if constexpr (F64) {
+    const int bq = q >> 2, jq = q & 3;
+    double acc[4][16];
 #pragma unroll
-        for (int m = 0; m < 16; ++m) acc[m] -= av * lb[kk][cg + 4 * m];
+    for (int y = 0; y < 16; ++y) {
+      const double *col = C + (4 * y + jq) * B + 8 * bq + 2 * g;
+#pragma unroll
+      for (int xh = 0; xh < 2; ++xh) {
+        double v[2];
+        *(uint4 *)&v[0] = *(const uint4 *)(col + 32 * xh);
+        acc[2 * xh][y] = -v[0];
+        acc[2 * xh + 1][y] = -v[1];
       }
     }
-  }
+    for (int s = 0; s < nch; ++s) {
+      stage(s);
 #pragma unroll
-  for (int m = 0; m < 16; ++m) C[(cg + 4 * m) * B + r] = (T)acc[m];
+      for (int ks = 0; ks < KC / 4; ++ks) {
+        const double *a = la + (4 * ks + g) * LDP + 2 * q;
+        const double *b = lb + (4 * ks + g) * LDP + jq;
+        double fa[4], fb[16];
+        *(uint4 *)&fa[0] = *(const uint4 *)(a);
+        *(uint4 *)&fa[2] = *(const uint4 *)(a + 32);
+#pragma unroll
+        for (int y = 0; y < 16; ++y) fb[y] = b[4 * y];
+#pragma unroll
+        for (int y = 0; y < 16; ++y)
+#pragma unroll
+          for (int x = 0; x < 4; ++x)
+            acc[x][y] = __builtin_amdgcn_mfma_f64_4x4x4f64(fa[x], fb[y], acc[x][y], 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int y = 0; y < 16; ++y) {
+      double *col = C + (4 * y + jq) * B + 8 * bq + 2 * g;
+#pragma unroll
+      for (int xh = 0; xh < 2; ++xh) {
+        double v[2] = {-acc[2 * xh][y], -acc[2 * xh + 1][y]};
+        *(uint4 *)(col + 32 * xh) = *(const uint4 *)&v[0];
+      }
+    }
+  } else {
+    v4f acc[4][4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      v4f x[4];
+      load_c_run(C + (4 * q + u) * B, g, x);
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+#pragma unroll
+        for (int s2 = 0; s2 < 4; ++s2) acc[s2][u][e] = -x[e][s2];
+    }
+    for (int s = 0; s < nch; ++s) {
+      stage(s);
+#pragma unroll
+      for (int ks = 0; ks < KC / 4; ++ks) {
+        float fa[4], fb[4];
+        *(uint4 *)&fa[0] = *(const uint4 *)(la + (4 * ks + g) * LDP + 4 * q);
+        *(uint4 *)&fb[0] = *(const uint4 *)(lb + (4 * ks + g) * LDP + 4 * q);
+#pragma unroll
+        for (int s2 = 0; s2 < 4; ++s2)
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+            acc[s2][u] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[s2], fb[u], acc[s2][u], 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      v4f x[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+#pragma unroll
+        for (int s2 = 0; s2 < 4; ++s2) x[e][s2] = -acc[s2][u][e];
+      store_c_run(C + (4 * q + u) * B, g, x);
+    }
+  }
 }
 
 }  // namespace
@@ -788,7 +882,7 @@ void launch_update(void *tiles, int store, int b, int64_t N, int64_t p0, int pw,
       hipLaunchKernelGGL(update_f32_kernel<1>, grid, dim3(256), 0, s, (float *)tiles, N, p0, pw,
                          k0, K, super_tile, G, G8, info);
   } else {
-    const dim3 grid((unsigned)G);
+    const dim3 grid((unsigned)((G + 3) / 4));  // four tiles (waves) per workgroup
     if (store == STORE_F64)
       hipLaunchKernelGGL(update64_kernel<double>, grid, dim3(256), 0, s, (double *)tiles, N, p0,
                          pw, k0, K, mode, super_tile, G, info);

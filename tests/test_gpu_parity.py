@@ -97,7 +97,7 @@ def test_known_l0_exact_solve():
 
 # -------------------------------------------------------- GP factors ---
 
-@pytest.mark.parametrize("n,tile", [(1024, 128), (1000, 128), (300, 64), (129, 128), (2, 64)])
+@pytest.mark.parametrize("n,tile", [(1024, 128), (1000, 128), (300, 64), (1000, 64), (129, 128), (2, 64)])
 def test_fp64_factor_parity(n, tile):
     X, _ = gp_inputs.gp_problem(n, seed=0)
     A = oracle.gp_assemble(X, 1.0, 1.0, 0.1)
@@ -128,7 +128,7 @@ def test_fp64_solve_parity(k):
         assert err <= 1e-10, (c, err)
 
 
-@pytest.mark.parametrize("n,tile", [(1000, 128), (333, 64)])
+@pytest.mark.parametrize("n,tile", [(1000, 128), (333, 64), (1000, 64)])
 def test_fp32_factor_backward_error(n, tile):
     X, _ = gp_inputs.gp_problem(n, seed=5)
     A = oracle.gp_assemble(X, 1.0, 1.0, 0.1)
@@ -159,9 +159,10 @@ def test_not_spd_info_matches_oracle():
     assert F.info() == info2
 
 
-def test_schedule_invariance_bitwise():
-    """Panel width and lookahead change the schedule, not the arithmetic."""
-    n = 1300
+@pytest.mark.parametrize("n,tile", [(1300, 128), (1000, 64)])
+def test_schedule_invariance_bitwise(n, tile):
+    """Panel width and lookahead change the schedule, not the arithmetic
+    (tile 64: the one-wave-per-tile matrix-core update, ragged last tile row)."""
     X, _ = gp_inputs.gp_problem(n, seed=3)
     A = dev(oracle.gp_assemble(X, 1.0, 1.0, 0.1))
     outs = []
@@ -172,7 +173,7 @@ def test_schedule_invariance_bitwise():
             P.set_option("lookahead", la)
             P.set_option("first_panel_width", fw)
             for prec in ("fp64", "fp32"):
-                F = P.chol_factor(A, prec, 128)
+                F = P.chol_factor(A, prec, tile)
                 outs.append((prec, host(P.chol_factor_to_dense(F))))
     finally:
         P.set_option("panel_width", 0)
