@@ -361,9 +361,12 @@ static void *panel_buf(const chol_factor_s *F, size_t p) {
   return (char *)F->p16 + (p & 1) * (size_t)F->N * (size_t)kP16BytesPerTileRow;
 }
 
-// Steps 1-2 (and the in-panel Step 3, in the storage precision) of panel
-// number p, columns [c0, c1); in the FP16 form the finished panel is then
-// converted for the updates that use it.
+// Steps 1-2 and the in-panel Step 3 of panel number p, columns [c0, c1).
+// In the FP16 form each finished tile column is converted into its two
+// chunks of the panel's FP16 buffer right after its panel solve, and the
+// in-panel update it feeds runs on the FP16 matrix cores from there, like
+// every other trailing update of that form; the buffer then holds the whole
+// converted panel for the updates right of it.
 static void factor_panel(chol_factor_s *F, size_t p, int64_t c0, int64_t c1, int st,
                          hipStream_t s) {
   const int64_t N = F->N;
@@ -371,10 +374,15 @@ static void factor_panel(chol_factor_s *F, size_t p, int64_t c0, int64_t c1, int
   for (int64_t c = c0; c < c1; ++c) {
     launch_potrf(F->tiles, st, b, N, c, F->d_info, s);
     launch_trsm(F->tiles, st, b, N, c, F->d_info, s);
+    void *col16 = nullptr;
+    if (F->p16) {
+      col16 = (char *)panel_buf(F, p) + 2 * (c - c0) * kP16BytesPerChunk;
+      launch_panel_f16(F->tiles, N, c, 1, col16, F->d_info, s);
+    }
     if (c + 1 < c1)
-      update(F->tiles, st, b, N, c, 1, c + 1, c1, /*band*/ 1, 8, /*fp16*/ 0, F->d_info, s);
+      update(F->tiles, st, b, N, c, 1, c + 1, c1, /*band*/ 1, 8, F->p16 ? 1 : 0, F->d_info, s, 0,
+             col16);
   }
-  if (F->p16) launch_panel_f16(F->tiles, N, c0, (int)(c1 - c0), panel_buf(F, p), F->d_info, s);
 }
 
 // The plain schedule (no lookahead) from tile column c_start on, for a

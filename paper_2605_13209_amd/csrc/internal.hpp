@@ -105,7 +105,8 @@ void set_f16_wide(int on);
 // [c0, N), in the update kernel's layout: p16 holds N * 32 chunks of
 // 128 x 64 halves per panel buffer (two 64-column chunks per tile column of
 // the panel, panel width <= 16).
-constexpr int64_t kP16BytesPerTileRow = 32 * 128 * 64 * 2;
+constexpr int64_t kP16BytesPerChunk = 128 * 64 * 2;  // 128 rows x 64 columns of halves
+constexpr int64_t kP16BytesPerTileRow = 32 * kP16BytesPerChunk;
 void launch_panel_f16(const void *tiles, int64_t N, int64_t c0, int pw, void *p16,
                       const int64_t *info, hipStream_t s);
 
