@@ -368,6 +368,12 @@ void chol_profile_reset(void);
  * "f16_wide"     : 1 (default) runs the FP16 form's whole-triangle updates
  *                  with 2 x 2 tiles per workgroup (half the operand traffic
  *                  per flop), 0 with one tile per workgroup; same result.
+ * "panel_order"  : order of the updates inside a panel: 1 right-looking
+ *                  (after each tile column, the panel's later columns are
+ *                  updated by it), 2 left-looking (before each tile column,
+ *                  it is updated by the panel's earlier columns: each panel
+ *                  tile read and written once), 0 (default) automatic: 2 for
+ *                  CHOL_FP16_SCALED, 1 otherwise.  Same factor bit for bit.
  * "bulk_wg_cap"  : with lookahead, the far trailing update runs with at most
  *                  this many (persistent) workgroups, leaving slots for the
  *                  next panel's kernels (default 0 = no cap: one workgroup

@@ -47,6 +47,7 @@ struct Options {
   std::atomic<int64_t> solve_spin_max{1 << 20};  // bound of each wait inside a solve
   std::atomic<int64_t> pcg_recompute{50};  // PCG: true residual every this many iterations
   std::atomic<int64_t> fp16_shift_c{32};   // FP16 retry: diagonal shift c * 2^-11 (0 = no retry)
+  std::atomic<int64_t> panel_order{0};  // in-panel updates: 0 automatic, 1 right-, 2 left-looking
 };
 Options g_opt;
 
@@ -264,6 +265,9 @@ int chol_set_option(const char *key, int64_t value) {
   } else if (!strcmp(key, "fp16_shift_c")) {
     if (value < 0 || value > 1024) return -2;
     g_opt.fp16_shift_c = value;
+  } else if (!strcmp(key, "panel_order")) {
+    if (value < 0 || value > 2) return -2;
+    g_opt.panel_order = value;
   } else if (!strcmp(key, "host_threads")) {
     if (value < 1 || value > 1024) return -2;
     host::set_threads((int)value);
@@ -286,6 +290,7 @@ int64_t chol_get_option(const char *key) {
   if (!strcmp(key, "solve_spin_max")) return g_opt.solve_spin_max;
   if (!strcmp(key, "pcg_recompute")) return g_opt.pcg_recompute;
   if (!strcmp(key, "fp16_shift_c")) return g_opt.fp16_shift_c;
+  if (!strcmp(key, "panel_order")) return g_opt.panel_order;
   if (!strcmp(key, "host_threads")) return host::threads();
   return -1;
 }
@@ -362,26 +367,36 @@ static void *panel_buf(const chol_factor_s *F, size_t p) {
 }
 
 // Steps 1-2 and the in-panel Step 3 of panel number p, columns [c0, c1).
+// The in-panel updates are either right-looking (after column c, one update
+// of the columns c+1 .. c1-1 of the panel by column c) or left-looking
+// (before column c, one update of column c by the columns c0 .. c-1).  Each
+// tile receives the same products in the same order either way (the update
+// kernels add the panel columns in increasing order and store C exactly), so
+// the factor is bitwise the same; left-looking reads and writes each tile of
+// the panel once instead of once per column to its left.
 // In the FP16 form each finished tile column is converted into its two
 // chunks of the panel's FP16 buffer right after its panel solve, and the
-// in-panel update it feeds runs on the FP16 matrix cores from there, like
-// every other trailing update of that form; the buffer then holds the whole
+// in-panel updates run on the FP16 matrix cores from there, like every
+// other trailing update of that form; the buffer then holds the whole
 // converted panel for the updates right of it.
 static void factor_panel(chol_factor_s *F, size_t p, int64_t c0, int64_t c1, int st,
                          hipStream_t s) {
   const int64_t N = F->N;
   const int b = F->b;
+  const int fp16 = F->p16 ? 1 : 0;
   for (int64_t c = c0; c < c1; ++c) {
+    if (F->inpanel_left && c > c0)
+      update(F->tiles, st, b, N, c0, (int)(c - c0), c, c + 1, /*band*/ 1, 8, fp16, F->d_info, s, 0,
+             panel_buf(F, p));
     launch_potrf(F->tiles, st, b, N, c, F->d_info, s);
     launch_trsm(F->tiles, st, b, N, c, F->d_info, s);
     void *col16 = nullptr;
-    if (F->p16) {
+    if (fp16) {
       col16 = (char *)panel_buf(F, p) + 2 * (c - c0) * kP16BytesPerChunk;
       launch_panel_f16(F->tiles, N, c, 1, col16, F->d_info, s);
     }
-    if (c + 1 < c1)
-      update(F->tiles, st, b, N, c, 1, c + 1, c1, /*band*/ 1, 8, F->p16 ? 1 : 0, F->d_info, s, 0,
-             col16);
+    if (!F->inpanel_left && c + 1 < c1)
+      update(F->tiles, st, b, N, c, 1, c + 1, c1, /*band*/ 1, 8, fp16, F->d_info, s, 0, col16);
   }
 }
 
@@ -555,12 +570,21 @@ int chol_factor_ex(const double *A, int64_t n, int64_t lda, int precision,
   const bool la = la_opt != 0 && N > w;
   const int64_t fw = g_opt.first_panel_width.load();
   const int64_t w0 = fw > 0 ? std::min<int64_t>(fw, w) : w;
+  // in-panel update order (same factor either way).  Automatic: left-looking
+  // for the FP16 form, whose in-panel updates are cheap on the matrix cores
+  // but move FP32 C tiles (n = 131072: 1036 against 1102 ms); right-looking
+  // otherwise, where the longer column chain of left-looking costs more than
+  // the traffic it saves (FP64 n = 1024: 0.90 against 1.26 ms; n = 65536:
+  // 1550 against 1562 ms; FP32 n = 65536 within 0.4 %).
+  const int64_t po = g_opt.panel_order.load();
+  F->inpanel_left = po == 2 || (po == 0 && precision == CHOL_FP16_SCALED);
 
 
   // Stream capture is not allowed on the legacy NULL stream: direct launches there.
   const bool graph = (opts && opts->graph >= 0 ? opts->graph != 0 : g_opt.graph != 0) &&
                      precision != CHOL_FP16_SCALED && !g_opt.profile && s != nullptr;
-  GraphKey gk{A, n, lda, precision, tile, w * 32 + w0, la ? 1 : 0, S, workspace};
+  GraphKey gk{A, n, lda, precision, tile, w * 32 + w0, (la ? 1 : 0) + (F->inpanel_left ? 2 : 0), S,
+              workspace};
   if (graph) {
     int dev = 0;
     (void)hipGetDevice(&dev);

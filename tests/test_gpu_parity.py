@@ -167,11 +167,14 @@ def test_schedule_invariance_bitwise(n, tile):
     A = dev(oracle.gp_assemble(X, 1.0, 1.0, 0.1))
     outs = []
     try:
-        for w, la, fw in [(1, 0, 0), (2, 1, 0), (4, 1, 0), (3, 0, 0), (8, 1, 0), (6, 0, 0), (16, 1, 0),
-                          (8, 1, 2), (4, 1, 1), (8, 0, 3)]:
+        # po: in-panel updates right-looking (1) or left-looking (2)
+        for w, la, fw, po in [(1, 0, 0, 1), (2, 1, 0, 2), (4, 1, 0, 1), (4, 1, 0, 2), (3, 0, 0, 2),
+                              (8, 1, 0, 1), (8, 1, 0, 2), (6, 0, 0, 1), (16, 1, 0, 2), (8, 1, 2, 2),
+                              (4, 1, 1, 1), (8, 0, 3, 2)]:
             P.set_option("panel_width", w)
             P.set_option("lookahead", la)
             P.set_option("first_panel_width", fw)
+            P.set_option("panel_order", po)
             for prec in ("fp64", "fp32"):
                 F = P.chol_factor(A, prec, tile)
                 outs.append((prec, host(P.chol_factor_to_dense(F))))
@@ -179,6 +182,7 @@ def test_schedule_invariance_bitwise(n, tile):
         P.set_option("panel_width", 0)
         P.set_option("lookahead", 1)
         P.set_option("first_panel_width", 0)
+        P.set_option("panel_order", 0)
     for prec in ("fp64", "fp32"):
         ref = [L for p, L in outs if p == prec]
         for L in ref[1:]:
@@ -485,16 +489,22 @@ def test_fp16_scaled_factor_and_refine():
 @pytest.mark.parametrize("pw,n", [(2, 1300), (3, 1300), (16, 2250)])
 def test_fp16_scaled_lookahead_invariance(pw, n):
     # the two FP16 panel buffers alternate between panels; with and without
-    # lookahead (ragged n, a partial last panel) the factors are identical;
-    # width 16 (the FP16 form's widest: 32 chunks of 64 columns per tile row)
+    # lookahead (ragged n, a partial last panel), with right- and left-looking
+    # in-panel updates, the factors are identical; width 16 (the FP16 form's
+    # widest: 32 chunks of 64 columns per tile row)
     X, _ = gp_inputs.gp_problem(n, seed=4)
     Ad = P.gp_assemble(torch.from_numpy(X).cuda(), 0.5, 1.0, 1.0)
     Ls = []
-    for la in (0, 1):
-        F = P.chol_factor(Ad, "fp16_scaled", 128, panel_width=pw, lookahead=la)
-        assert F.info() == 0
-        Ls.append(host(P.chol_factor_to_dense(F)))
-    assert np.array_equal(Ls[0], Ls[1])
+    try:
+        for la, po in ((0, 1), (1, 1), (0, 2), (1, 2)):
+            P.set_option("panel_order", po)
+            F = P.chol_factor(Ad, "fp16_scaled", 128, panel_width=pw, lookahead=la)
+            assert F.info() == 0
+            Ls.append(host(P.chol_factor_to_dense(F)))
+    finally:
+        P.set_option("panel_order", 0)
+    for L in Ls[1:]:
+        assert np.array_equal(Ls[0], L)
     be = oracle.backward_error(oracle.gp_assemble(X, 0.5, 1.0, 1.0), Ls[0])
     assert be <= 5e-3, be
 
