@@ -374,6 +374,11 @@ void chol_profile_reset(void);
  *                  it is updated by the panel's earlier columns: each panel
  *                  tile read and written once), 0 (default) automatic: 2 for
  *                  CHOL_FP16_SCALED, 1 otherwise.  Same factor bit for bit.
+ * "trsm_split"   : column steps with at most this many tiles below the
+ *                  diagonal split each tile's panel solve (Step 2) over four
+ *                  workgroups, a quarter of its rows each, which shortens
+ *                  the column chain of small matrices and of the last
+ *                  columns (default 64; 0 = never).  Same factor bit for bit.
  * "bulk_wg_cap"  : with lookahead, the far trailing update runs with at most
  *                  this many (persistent) workgroups, leaving slots for the
  *                  next panel's kernels (default 0 = no cap: one workgroup

@@ -48,6 +48,7 @@ struct Options {
   std::atomic<int64_t> pcg_recompute{50};  // PCG: true residual every this many iterations
   std::atomic<int64_t> fp16_shift_c{32};   // FP16 retry: diagonal shift c * 2^-11 (0 = no retry)
   std::atomic<int64_t> panel_order{0};  // in-panel updates: 0 automatic, 1 right-, 2 left-looking
+  std::atomic<int64_t> trsm_split{64};  // panel solves split by rows up to this many tiles
 };
 Options g_opt;
 
@@ -265,6 +266,10 @@ int chol_set_option(const char *key, int64_t value) {
   } else if (!strcmp(key, "fp16_shift_c")) {
     if (value < 0 || value > 1024) return -2;
     g_opt.fp16_shift_c = value;
+  } else if (!strcmp(key, "trsm_split")) {
+    if (value < 0 || value > (int64_t)1 << 30) return -2;
+    g_opt.trsm_split = value;
+    set_trsm_split_max(value);
   } else if (!strcmp(key, "panel_order")) {
     if (value < 0 || value > 2) return -2;
     g_opt.panel_order = value;
@@ -291,6 +296,7 @@ int64_t chol_get_option(const char *key) {
   if (!strcmp(key, "pcg_recompute")) return g_opt.pcg_recompute;
   if (!strcmp(key, "fp16_shift_c")) return g_opt.fp16_shift_c;
   if (!strcmp(key, "panel_order")) return g_opt.panel_order;
+  if (!strcmp(key, "trsm_split")) return g_opt.trsm_split;
   if (!strcmp(key, "host_threads")) return host::threads();
   return -1;
 }

@@ -84,6 +84,9 @@ void launch_potrf(void *tiles, int store, int b, int64_t N, int64_t c, int64_t *
                   hipStream_t s);
 // Step 2: tiles (i, c), i in [r0, N) (r0 <= 0: c + 1): X <- X L_cc^{-T}
 // (FP64 arithmetic).
+// Panel solves of column steps with at most this many tiles below the
+// diagonal run with four workgroups per tile (a quarter of the rows each).
+void set_trsm_split_max(int64_t tiles);
 void launch_trsm(void *tiles, int store, int b, int64_t N, int64_t c, const int64_t *info,
                  hipStream_t s, int64_t r0 = 0);
 // Step 3: C_ik -= sum_{p in [p0, p0+pw)} L_ip L_kp^T over the region

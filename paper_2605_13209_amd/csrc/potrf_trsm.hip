@@ -252,9 +252,14 @@ __global__ __launch_bounds__(256) void potrf_kernel(T *__restrict__ tiles, int64
 //       while the block loop is not unrolled).
 // IDENT: the right-hand side is the identity (X is only written), which
 // gives X = L^{-T}: the inverted diagonal blocks of the solves.
-template <int B, typename T, bool IDENT>
-__device__ __forceinline__ void trsm_tile(const T *__restrict__ L, T *__restrict__ X) {
-  constexpr int M = B / 16, NB = 16, PP = NB + 2;
+// RB < B: the workgroup solves only rows [r0, r0 + RB) of the tile (the rows
+// are independent), so B / RB workgroups share a tile; thread (tr, tc) then
+// owns elements (r0 + tr + 16 m, tc + 16 n), m < RB / 16, and the column
+// updates shrink with the rows, while the row solves (2) keep their length.
+template <int B, typename T, bool IDENT, int RB = B>
+__device__ __forceinline__ void trsm_tile(const T *__restrict__ L, T *__restrict__ X, int r0 = 0) {
+  static_assert(!IDENT || RB == B, "the identity right-hand side is solved whole");
+  constexpr int M = B / 16, MR = RB / 16, NB = 16, PP = NB + 2;
   constexpr int PF = (B * NB + 255) / 256;                  // prefetched L values per thread
   __shared__ __attribute__((aligned(16))) double ls[2][B * PP];  // L column blocks
   __shared__ __attribute__((aligned(16))) double px[B * PP];     // current block of X
@@ -277,22 +282,26 @@ __device__ __forceinline__ void trsm_tile(const T *__restrict__ L, T *__restrict
       if (e < rows * NB) ls[q & 1][r * PP + u] = v[x];
     }
   };
-  double a[M][M];
+  double a[MR][M];
   if (IDENT) {
 #pragma unroll
     for (int m = 0; m < M; ++m)
 #pragma unroll
       for (int n = 0; n < M; ++n) a[m][n] = (tr + 16 * m == tc + 16 * n) ? 1.0 : 0.0;
   } else {
-    // the tile into registers through LDS (the L buffers, not yet in use), a
-    // quarter of 32 columns at a time with contiguous reads, the next
-    // quarter's loads in flight while the current one is redistributed
-    constexpr int QC = 32, LD = B + 1, QV = QC * B / 256;
+    // the rows into registers through LDS (the L buffers, not yet in use),
+    // 32 columns at a time with contiguous reads, the next group's loads in
+    // flight while the current one is redistributed
+    constexpr int QC = 32, LD = RB + 1, QV = QC * RB / 256;
     static_assert(QC * LD <= 2 * B * PP, "staging fits in the L buffers");
     double *stg = &ls[0][0];
+    auto src = [&](int q4, int x) -> const T & {
+      const int e = t + 256 * x, r = e % RB, cc = e / RB;
+      return X[(int64_t)(q4 * QC + cc) * B + r0 + r];
+    };
     T nxt[QV];
 #pragma unroll
-    for (int x = 0; x < QV; ++x) nxt[x] = X[t + 256 * x];
+    for (int x = 0; x < QV; ++x) nxt[x] = src(0, x);
 #pragma unroll
     for (int q4 = 0; q4 < B / QC; ++q4) {
       T cur[QV];
@@ -300,17 +309,17 @@ __device__ __forceinline__ void trsm_tile(const T *__restrict__ L, T *__restrict
       for (int x = 0; x < QV; ++x) cur[x] = nxt[x];
       if (q4 + 1 < B / QC) {
 #pragma unroll
-        for (int x = 0; x < QV; ++x) nxt[x] = X[(int64_t)(q4 + 1) * QC * B + t + 256 * x];
+        for (int x = 0; x < QV; ++x) nxt[x] = src(q4 + 1, x);
       }
-      if (q4 > 0) __syncthreads();  // previous quarter fully read
+      if (q4 > 0) __syncthreads();  // previous group fully read
 #pragma unroll
       for (int x = 0; x < QV; ++x) {
-        const int e = t + 256 * x, r = e % B, cc = e / B;
+        const int e = t + 256 * x, r = e % RB, cc = e / RB;
         stg[cc * LD + r] = (double)cur[x];
       }
       __syncthreads();
 #pragma unroll
-      for (int m = 0; m < M; ++m)
+      for (int m = 0; m < MR; ++m)
 #pragma unroll
         for (int nn = 0; nn < 2; ++nn)
           a[m][2 * q4 + nn] = stg[(tc + 16 * nn) * LD + tr + 16 * m];
@@ -329,10 +338,10 @@ __device__ __forceinline__ void trsm_tile(const T *__restrict__ L, T *__restrict
     double nxt[PF];
     // (1) block q of X to LDS
 #pragma unroll
-    for (int m = 0; m < M; ++m) px[(tr + 16 * m) * PP + tc] = a[m][0];
+    for (int m = 0; m < MR; ++m) px[(tr + 16 * m) * PP + tc] = a[m][0];
     __syncthreads();
     // (2) one thread per row: x L_qq^T = rhs
-    if (t < B) {
+    if (t < RB) {
       double x[NB];
 #pragma unroll
       for (int j = 0; j < NB; j += 2) *(double2 *)&x[j] = *(const double2 *)&px[t * PP + j];
@@ -344,22 +353,22 @@ __device__ __forceinline__ void trsm_tile(const T *__restrict__ L, T *__restrict
     // the next column block of L is loaded while this block is applied
     if (q + 1 < M) lget(q + 1, nxt);
     // (3) the solved block to HBM; update of the remaining columns
-    for (int e = t; e < B * NB; e += 256) {
-      const int r = e % B, u = e / B;
-      X[(int64_t)(16 * q + u) * B + r] = (T)px[r * PP + u];
+    for (int e = t; e < RB * NB; e += 256) {
+      const int r = e % RB, u = e / RB;
+      X[(int64_t)(16 * q + u) * B + r0 + r] = (T)px[r * PP + u];
     }
 #pragma unroll
     for (int k = 0; k < NB; k += 2) {
-      double2 xr[M], lc[M];
+      double2 xr[MR], lc[M];
 #pragma unroll
-      for (int m = 0; m < M; ++m) xr[m] = *(const double2 *)&px[(tr + 16 * m) * PP + k];
+      for (int m = 0; m < MR; ++m) xr[m] = *(const double2 *)&px[(tr + 16 * m) * PP + k];
 #pragma unroll
       for (int n = 1; n < M; ++n) lc[n] = *(const double2 *)&lq[(tc + 16 * n) * PP + k];
 #pragma unroll
       for (int n = 1; n < M; ++n)
         if (n < M - q) {
 #pragma unroll
-          for (int m = 0; m < M; ++m) {
+          for (int m = 0; m < MR; ++m) {
             a[m][n] -= xr[m].x * lc[n].x;
             a[m][n] -= xr[m].y * lc[n].y;
           }
@@ -370,19 +379,22 @@ __device__ __forceinline__ void trsm_tile(const T *__restrict__ L, T *__restrict
     __syncthreads();
     // (4) shift: the next block column moves to register index 0
 #pragma unroll
-    for (int m = 0; m < M; ++m)
+    for (int m = 0; m < MR; ++m)
 #pragma unroll
       for (int n = 0; n + 1 < M; ++n) a[m][n] = a[m][n + 1];
   }
 }
 
-template <int B, typename T>
+// B / RB workgroups per tile, each solving RB of its rows.
+template <int B, typename T, int RB>
 __global__ __launch_bounds__(256) void trsm_kernel(T *__restrict__ tiles, int64_t N, int64_t c,
                                                    int64_t r0, const int64_t *__restrict__ info) {
   if (*info != 0) return;
-  const int64_t i = r0 + blockIdx.x;
-  trsm_tile<B, T, false>(tiles + tile_index(c, c, N) * (int64_t)(B * B),
-                         tiles + tile_index(i, c, N) * (int64_t)(B * B));
+  constexpr int SPLIT = B / RB;
+  const int64_t i = r0 + blockIdx.x / SPLIT;
+  trsm_tile<B, T, false, RB>(tiles + tile_index(c, c, N) * (int64_t)(B * B),
+                             tiles + tile_index(i, c, N) * (int64_t)(B * B),
+                             (int)(blockIdx.x % SPLIT) * RB);
 }
 
 // Inverted diagonal blocks for the solves: block c of dinv = L_cc^{-T}
@@ -435,21 +447,39 @@ void potrf_dispatch(void *tiles, int store, int64_t N, int64_t c, int64_t *info,
                        info);
 }
 
+// Column steps with at most this many tiles below the diagonal split each
+// tile's panel solve over four workgroups (option "trsm_split").
+int64_t g_trsm_split_max = 64;
+
 template <int B>
 void trsm_dispatch(void *tiles, int store, int64_t N, int64_t c, const int64_t *info,
                    hipStream_t s, int64_t r0) {
   if (r0 <= c) r0 = c + 1;
   const int64_t nt = N - r0;
   if (nt <= 0) return;
-  if (store == STORE_F64)
-    hipLaunchKernelGGL((trsm_kernel<B, double>), dim3((unsigned)nt), dim3(256), 0, s,
+  // few tiles (small matrices, the last columns): four workgroups per tile,
+  // a quarter of the rows each, for a shorter chain; whole tiles otherwise
+  if (nt <= g_trsm_split_max) {
+    constexpr int RB = B / 4;
+    const dim3 grid((unsigned)(4 * nt));
+    if (store == STORE_F64)
+      hipLaunchKernelGGL((trsm_kernel<B, double, RB>), grid, dim3(256), 0, s, (double *)tiles, N,
+                         c, r0, info);
+    else
+      hipLaunchKernelGGL((trsm_kernel<B, float, RB>), grid, dim3(256), 0, s, (float *)tiles, N, c,
+                         r0, info);
+  } else if (store == STORE_F64) {
+    hipLaunchKernelGGL((trsm_kernel<B, double, B>), dim3((unsigned)nt), dim3(256), 0, s,
                        (double *)tiles, N, c, r0, info);
-  else
-    hipLaunchKernelGGL((trsm_kernel<B, float>), dim3((unsigned)nt), dim3(256), 0, s,
+  } else {
+    hipLaunchKernelGGL((trsm_kernel<B, float, B>), dim3((unsigned)nt), dim3(256), 0, s,
                        (float *)tiles, N, c, r0, info);
+  }
 }
 
 }  // namespace
+
+void set_trsm_split_max(int64_t tiles) { g_trsm_split_max = tiles; }
 
 void launch_potrf(void *tiles, int store, int b, int64_t N, int64_t c, int64_t *info,
                   hipStream_t s) {

@@ -189,6 +189,26 @@ def test_schedule_invariance_bitwise(n, tile):
             assert np.array_equal(L, ref[0])
 
 
+@pytest.mark.parametrize("n,tile", [(1300, 128), (1000, 64)])
+def test_trsm_split_bitwise(n, tile):
+    """Panel solves split over four workgroups per tile (a quarter of the rows
+    each) give the same factor as whole-tile panel solves."""
+    X, _ = gp_inputs.gp_problem(n, seed=9)
+    A = dev(oracle.gp_assemble(X, 1.0, 1.0, 0.1))
+    old = P.get_option("trsm_split")
+    try:
+        for prec in ("fp64", "fp32"):
+            Ls = []
+            for split in (0, 1 << 20, 3):
+                P.set_option("trsm_split", split)
+                F = P.chol_factor(A, prec, tile)
+                assert F.info() == 0
+                Ls.append(host(P.chol_factor_to_dense(F)))
+            assert np.array_equal(Ls[0], Ls[1]) and np.array_equal(Ls[0], Ls[2])
+    finally:
+        P.set_option("trsm_split", old)
+
+
 def test_repeatable_bitwise():
     n = 900
     X, _ = gp_inputs.gp_problem(n, seed=4)
