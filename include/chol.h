@@ -379,6 +379,11 @@ void chol_profile_reset(void);
  *                  workgroups, a quarter of its rows each, which shortens
  *                  the column chain of small matrices and of the last
  *                  columns (default 64; 0 = never).  Same factor bit for bit.
+ * "potrf_lookahead": 1 factors each diagonal tile (Step 1) with a fifth
+ *                  wave that factors the next 16 x 16 diagonal block while
+ *                  the other four apply the current block's update; 0
+ *                  without; 2 (default) automatic: with it below 64 tile
+ *                  rows.  Same factor bit for bit.
  * "bulk_wg_cap"  : with lookahead, the far trailing update runs with at most
  *                  this many (persistent) workgroups, leaving slots for the
  *                  next panel's kernels (default 0 = no cap: one workgroup

@@ -49,6 +49,7 @@ struct Options {
   std::atomic<int64_t> fp16_shift_c{32};   // FP16 retry: diagonal shift c * 2^-11 (0 = no retry)
   std::atomic<int64_t> panel_order{0};  // in-panel updates: 0 automatic, 1 right-, 2 left-looking
   std::atomic<int64_t> trsm_split{64};  // panel solves split by rows up to this many tiles
+  std::atomic<int64_t> potrf_lookahead{2};  // fifth-wave POTRF: 0 never, 1 always, 2 automatic
 };
 Options g_opt;
 
@@ -270,6 +271,9 @@ int chol_set_option(const char *key, int64_t value) {
     if (value < 0 || value > (int64_t)1 << 30) return -2;
     g_opt.trsm_split = value;
     set_trsm_split_max(value);
+  } else if (!strcmp(key, "potrf_lookahead")) {
+    if (value < 0 || value > 2) return -2;
+    g_opt.potrf_lookahead = value;
   } else if (!strcmp(key, "panel_order")) {
     if (value < 0 || value > 2) return -2;
     g_opt.panel_order = value;
@@ -297,6 +301,7 @@ int64_t chol_get_option(const char *key) {
   if (!strcmp(key, "fp16_shift_c")) return g_opt.fp16_shift_c;
   if (!strcmp(key, "panel_order")) return g_opt.panel_order;
   if (!strcmp(key, "trsm_split")) return g_opt.trsm_split;
+  if (!strcmp(key, "potrf_lookahead")) return g_opt.potrf_lookahead;
   if (!strcmp(key, "host_threads")) return host::threads();
   return -1;
 }
@@ -394,7 +399,7 @@ static void factor_panel(chol_factor_s *F, size_t p, int64_t c0, int64_t c1, int
     if (F->inpanel_left && c > c0)
       update(F->tiles, st, b, N, c0, (int)(c - c0), c, c + 1, /*band*/ 1, 8, fp16, F->d_info, s, 0,
              panel_buf(F, p));
-    launch_potrf(F->tiles, st, b, N, c, F->d_info, s);
+    launch_potrf(F->tiles, st, b, N, c, F->d_info, s, F->potrf_la);
     launch_trsm(F->tiles, st, b, N, c, F->d_info, s);
     void *col16 = nullptr;
     if (fp16) {
@@ -584,13 +589,21 @@ int chol_factor_ex(const double *A, int64_t n, int64_t lda, int precision,
   // 1550 against 1562 ms; FP32 n = 65536 within 0.4 %).
   const int64_t po = g_opt.panel_order.load();
   F->inpanel_left = po == 2 || (po == 0 && precision == CHOL_FP16_SCALED);
+  // diagonal factorisations with the fifth-wave lookahead (same factor):
+  // automatic below 64 tile rows, where the column chain is the whole
+  // factorisation (n = 1024: 0.86 -> 0.77 ms); from there on the diagonal
+  // factorisation runs beside the trailing update, whose workgroups leave
+  // room for four waves more readily than for five (n = 32768: 203 against
+  // 208 ms with it)
+  const int64_t pl = g_opt.potrf_lookahead.load();
+  F->potrf_la = pl == 1 || (pl == 2 && N < 64);
 
 
   // Stream capture is not allowed on the legacy NULL stream: direct launches there.
   const bool graph = (opts && opts->graph >= 0 ? opts->graph != 0 : g_opt.graph != 0) &&
                      precision != CHOL_FP16_SCALED && !g_opt.profile && s != nullptr;
-  GraphKey gk{A, n, lda, precision, tile, w * 32 + w0, (la ? 1 : 0) + (F->inpanel_left ? 2 : 0), S,
-              workspace};
+  GraphKey gk{A, n, lda, precision, tile, w * 32 + w0,
+              (la ? 1 : 0) + (F->inpanel_left ? 2 : 0) + (F->potrf_la ? 4 : 0), S, workspace};
   if (graph) {
     int dev = 0;
     (void)hipGetDevice(&dev);

@@ -80,8 +80,10 @@ void launch_unpack(const void *tiles, int store, int b, int64_t N, int64_t n, do
                    double *L, int64_t ldl, const int64_t *info, hipStream_t s);
 
 // Step 1: factor diagonal tile c in place (FP64 arithmetic).  Sets *info.
+// la: with the fifth-wave lookahead inside the tile (same result; faster
+// alone, but its fifth wave is harder to place beside trailing updates).
 void launch_potrf(void *tiles, int store, int b, int64_t N, int64_t c, int64_t *info,
-                  hipStream_t s);
+                  hipStream_t s, bool la = false);
 // Step 2: tiles (i, c), i in [r0, N) (r0 <= 0: c + 1): X <- X L_cc^{-T}
 // (FP64 arithmetic).
 // Panel solves of column steps with at most this many tiles below the

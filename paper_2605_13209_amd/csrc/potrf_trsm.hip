@@ -74,9 +74,17 @@ __device__ __forceinline__ void row_solve(double (&x)[NB], const double *l, cons
 // So a tile costs 5 barriers per 16 columns instead of 2 per column.  A
 // failed pivot is reported by the wave of step (2) and every thread leaves
 // after the barrier.  The tile is loaded through LDS a quarter at a time
-// (contiguous global reads).  256 threads, LDS below 36 KB: the kernel fits
-// on a CU beside one trailing-update workgroup.
-template <int B, typename T>
+// (contiguous global reads).  LDS below 36 KB.
+//
+// LA (lookahead inside the tile, 320 threads): a fifth wave holds no tile
+// elements and does every 16 x 16 diagonal factorisation.  In block kb the
+// owners first apply block kb's rank-16 update to the next diagonal block
+// alone and hand it over through LDS; the fifth wave factors it while the
+// owners apply the rest of the update and store block kb's columns.  The
+// diagonal chain (16 dependent pivots) then runs beside the update instead
+// of after it.  Every element sees the same operations in the same order
+// as without lookahead, so the factor is bitwise the same.
+template <int B, typename T, bool LA = false>
 __device__ __forceinline__ void potrf_body(T *__restrict__ tiles, int64_t N, int64_t c,
                                            int64_t *__restrict__ info) {
   if (*info != 0) return;
@@ -85,101 +93,128 @@ __device__ __forceinline__ void potrf_body(T *__restrict__ tiles, int64_t N, int
   constexpr int PP = NB + 2;  // pitch of the diagonal block and the panel (16-byte rows)
   constexpr int QC = 32;      // columns per staging quarter
   constexpr int LD = B + 1;
-  constexpr int WORK = NB * PP + (B - NB) * PP + 2 * NB;
+  constexpr int WORK = 2 * NB * PP + (B - NB) * PP + 4 * NB;
   constexpr int SMEM = (QC * LD > WORK) ? QC * LD : WORK;
+  constexpr int DW = LA ? 256 : 0;  // first thread of the wave that factors diagonal blocks
   __shared__ __attribute__((aligned(16))) double sm[SMEM];
   __shared__ int fail;
-  double *stage = sm;               // QC x LD, while loading
-  double *dg = sm;                  // NB x PP diagonal block
-  double *pn = sm + NB * PP;        // (B - NB) x PP panel below it
-  double *cb = pn + (B - NB) * PP;  // column broadcast of step (2)
-  double *rd = cb + NB;             // reciprocal diagonal of the block
+  double *stage = sm;                        // QC x LD, while loading
+  double *pn = sm + 2 * NB * PP;             // (B - NB) x PP panel below the diagonal block
+  double *cb = pn + (B - NB) * PP;           // column broadcast of the factorisation
+  // diagonal blocks (NB x PP) and their reciprocal diagonals, alternating by block
+  auto dgs = [&](int kb) { return sm + (kb & 1) * NB * PP; };
+  auto rds = [&](int kb) { return cb + NB + (kb & 1) * NB; };
   T *tile = tiles + tile_index(c, c, N) * (int64_t)(B * B);
-  const int t = threadIdx.x, tc = t & 15, tr = t >> 4;
+  const int t = threadIdx.x, tc = t & 15, tr = (t >> 4) & 15;
+  const bool owner = t < 256;
   if (t == 0) fail = 0;
   double a[M][M];
   {
     // all loads of a quarter are issued before any LDS store (one latency per quarter)
     constexpr int QV = QC * B / 256;
     T nxt[QV];
+    if (owner) {
 #pragma unroll
-    for (int x = 0; x < QV; ++x) nxt[x] = tile[t + 256 * x];
+      for (int x = 0; x < QV; ++x) nxt[x] = tile[t + 256 * x];
+    }
 #pragma unroll
     for (int q4 = 0; q4 < B / QC; ++q4) {
       T cur[QV];
+      if (owner) {
 #pragma unroll
-      for (int x = 0; x < QV; ++x) cur[x] = nxt[x];
-      if (q4 + 1 < B / QC) {
+        for (int x = 0; x < QV; ++x) cur[x] = nxt[x];
+        if (q4 + 1 < B / QC) {
 #pragma unroll
-        for (int x = 0; x < QV; ++x) nxt[x] = tile[(q4 + 1) * QC * B + t + 256 * x];
-      }
+          for (int x = 0; x < QV; ++x) nxt[x] = tile[(q4 + 1) * QC * B + t + 256 * x];
+        }
 #pragma unroll
-      for (int x = 0; x < QV; ++x) {
-        const int e = t + 256 * x, r = e % B, cc = e / B;
-        stage[cc * LD + r] = (double)cur[x];
+        for (int x = 0; x < QV; ++x) {
+          const int e = t + 256 * x, r = e % B, cc = e / B;
+          stage[cc * LD + r] = (double)cur[x];
+        }
       }
       __syncthreads();
+      if (owner) {
 #pragma unroll
-      for (int m = 0; m < M; ++m)
+        for (int m = 0; m < M; ++m)
 #pragma unroll
-        for (int nn = 0; nn < 2; ++nn)
-          a[m][2 * q4 + nn] = stage[(tc + 16 * nn) * LD + tr + 16 * m];
+          for (int nn = 0; nn < 2; ++nn)
+            a[m][2 * q4 + nn] = stage[(tc + 16 * nn) * LD + tr + 16 * m];
+      }
       __syncthreads();
     }
   }
 
+  // one wave (lanes l = t - DW) factors the 16 x 16 block dg in place and
+  // leaves its reciprocal diagonal in rd; returns the first failed pivot
+  // (1-based) of block kb through info / fail
+  auto factor_diag = [&](double *dg, double *rd, int kb) {
+    const int l = t - DW;
+    double x[NB];
+#pragma unroll
+    for (int j = 0; j < NB; ++j) x[j] = (l < NB) ? dg[l * PP + j] : 0.0;
+    int bad = 0;  // first failed pivot (1-based); uniform across the wave
+#pragma unroll
+    for (int k = 0; k < NB; ++k) {
+      double d = readlane_f64(x[k], k);
+      if (!(d > 0.0)) {
+        if (!bad) bad = k + 1;
+        d = 1.0;  // keep going without NaNs; the result is discarded
+      }
+      // the pivot's reciprocal square root, and the square root as d times
+      // it: one rounding more than a correctly rounded sqrt, but the
+      // latter's refinement chain was the longest part of this loop
+      // (POTRF 58.6 -> 48.7 us); exact for the powers of four that the
+      // exact-arithmetic inputs produce
+      const double rl = rsqrt(d);
+      const double lkk = d * rl;
+      x[k] = (l == k) ? lkk : (l > k ? x[k] * rl : x[k]);
+      if (l == k) rd[k] = rl;
+      if (l < NB) cb[l] = x[k];
+#pragma unroll
+      for (int j = k + 1; j < NB; ++j) x[j] -= x[k] * cb[j];
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    if (bad) {
+      if (l == 0) {
+        *info = c * B + kb * NB + bad;
+        fail = 1;
+      }
+    } else if (l < NB) {
+#pragma unroll
+      for (int j = 0; j < NB; ++j) dg[l * PP + j] = x[j];
+    }
+  };
+
+  if (LA) {
+    // the first diagonal block, factored before the loop
+    if (owner) dgs(0)[tr * PP + tc] = a[0][0];
+    __syncthreads();
+    if (t >= DW) factor_diag(dgs(0), rds(0), 0);
+    __syncthreads();
+    if (fail) return;  // uniform
+  }
 #pragma unroll 1
   for (int kb = 0; kb < M; ++kb) {
     const int rem = M - kb;  // register blocks still trailing
-    // (1) diagonal block to LDS
-    dg[tr * PP + tc] = a[0][0];
-    __syncthreads();
-    // (2) one wave factors it
-    if (t < 64) {
-      const int l = t;
-      double x[NB];
-#pragma unroll
-      for (int j = 0; j < NB; ++j) x[j] = (l < NB) ? dg[l * PP + j] : 0.0;
-      int bad = 0;  // first failed pivot (1-based); uniform across the wave
-#pragma unroll
-      for (int k = 0; k < NB; ++k) {
-        double d = readlane_f64(x[k], k);
-        if (!(d > 0.0)) {
-          if (!bad) bad = k + 1;
-          d = 1.0;  // keep going without NaNs; the result is discarded
-        }
-        // the pivot's reciprocal square root, and the square root as d times
-        // it: one rounding more than a correctly rounded sqrt, but the
-        // latter's refinement chain was the longest part of this loop
-        // (POTRF 58.6 -> 48.7 us); exact for the powers of four that the
-        // exact-arithmetic inputs produce
-        const double rl = rsqrt(d);
-        const double lkk = d * rl;
-        x[k] = (l == k) ? lkk : (l > k ? x[k] * rl : x[k]);
-        if (l == k) rd[k] = rl;
-        if (l < NB) cb[l] = x[k];
-#pragma unroll
-        for (int j = k + 1; j < NB; ++j) x[j] -= x[k] * cb[j];
-        __builtin_amdgcn_sched_barrier(0);
-      }
-      if (bad) {
-        if (l == 0) {
-          *info = c * B + kb * NB + bad;
-          fail = 1;
-        }
-      } else if (l < NB) {
-#pragma unroll
-        for (int j = 0; j < NB; ++j) dg[l * PP + j] = x[j];
-      }
+    double *dg = dgs(kb), *rd = rds(kb);
+    if (!LA) {
+      // (1) diagonal block to LDS
+      dg[tr * PP + tc] = a[0][0];
+      __syncthreads();
+      // (2) one wave factors it
+      if (t < 64) factor_diag(dg, rd, kb);
+      __syncthreads();
+      if (fail) return;  // uniform
     }
-    __syncthreads();
-    if (fail) return;  // uniform
     if (kb + 1 < M) {
       // (3) panel below to LDS, solved row by row
       const int PR = B - NB * (kb + 1);
+      if (owner) {
 #pragma unroll
-      for (int m = 1; m < M; ++m)
-        if (m < rem) pn[(tr + 16 * (m - 1)) * PP + tc] = a[m][0];
+        for (int m = 1; m < M; ++m)
+          if (m < rem) pn[(tr + 16 * (m - 1)) * PP + tc] = a[m][0];
+      }
       __syncthreads();
       if (t < PR) {
         double x[NB];
@@ -190,36 +225,58 @@ __device__ __forceinline__ void potrf_body(T *__restrict__ tiles, int64_t N, int
         for (int j = 0; j < NB; j += 2) *(double2 *)&pn[t * PP + j] = *(const double2 *)&x[j];
       }
       __syncthreads();
-      // (4) rank-16 update of the trailing elements (blocks m >= n >= 1)
+      if (LA) {
+        // (4a) the next diagonal block's update first, handed to the fifth wave
+        if (owner) {
 #pragma unroll
-      for (int k = 0; k < NB; k += 2) {
-        double2 pr[M], pc[M];
-#pragma unroll
-        for (int m = 1; m < M; ++m) {
-          pr[m] = *(const double2 *)&pn[(tr + 16 * (m - 1)) * PP + k];
-          pc[m] = *(const double2 *)&pn[(tc + 16 * (m - 1)) * PP + k];
-        }
-#pragma unroll
-        for (int m = 1; m < M; ++m)
-          if (m < rem) {
-#pragma unroll
-            for (int n = 1; n <= m; ++n) {
-              a[m][n] -= pr[m].x * pc[n].x;
-              a[m][n] -= pr[m].y * pc[n].y;
-            }
+          for (int k = 0; k < NB; k += 2) {
+            const double2 pr = *(const double2 *)&pn[tr * PP + k];
+            const double2 pc = *(const double2 *)&pn[tc * PP + k];
+            a[1][1] -= pr.x * pc.x;
+            a[1][1] -= pr.y * pc.y;
           }
-        __builtin_amdgcn_sched_barrier(0);
+          dgs(kb + 1)[tr * PP + tc] = a[1][1];
+        }
+        __syncthreads();
+        if (t >= DW) factor_diag(dgs(kb + 1), rds(kb + 1), kb + 1);
+      }
+      // (4) rank-16 update of the trailing elements (blocks m >= n >= 1;
+      // with LA the block (1, 1) is done)
+      if (owner) {
+#pragma unroll
+        for (int k = 0; k < NB; k += 2) {
+          double2 pr[M], pc[M];
+#pragma unroll
+          for (int m = 1; m < M; ++m) {
+            pr[m] = *(const double2 *)&pn[(tr + 16 * (m - 1)) * PP + k];
+            pc[m] = *(const double2 *)&pn[(tc + 16 * (m - 1)) * PP + k];
+          }
+#pragma unroll
+          for (int m = 1; m < M; ++m)
+            if (m < rem) {
+#pragma unroll
+              for (int n = 1; n <= m; ++n) {
+                if (LA && m == 1 && n == 1) continue;
+                a[m][n] -= pr[m].x * pc[n].x;
+                a[m][n] -= pr[m].y * pc[n].y;
+              }
+            }
+          __builtin_amdgcn_sched_barrier(0);
+        }
       }
     }
     // the finished 16 columns (zero above the diagonal) from LDS to HBM
-    const int j0 = NB * kb;
-    for (int e = t; e < NB * B; e += 256) {
-      const int r = e % B, jj = e / B, j = j0 + jj;
-      double v = 0.0;
-      if (r >= j) v = (r < j0 + NB) ? dg[(r - j0) * PP + jj] : pn[(r - j0 - NB) * PP + jj];
-      tile[(int64_t)j * B + r] = (T)v;
+    if (owner) {
+      const int j0 = NB * kb;
+      for (int e = t; e < NB * B; e += 256) {
+        const int r = e % B, jj = e / B, j = j0 + jj;
+        double v = 0.0;
+        if (r >= j) v = (r < j0 + NB) ? dg[(r - j0) * PP + jj] : pn[(r - j0 - NB) * PP + jj];
+        tile[(int64_t)j * B + r] = (T)v;
+      }
     }
     __syncthreads();
+    if (LA && fail) return;  // the next diagonal block failed (uniform)
     // (5) shift: the next diagonal block moves to register index 0
 #pragma unroll
     for (int m = 0; m + 1 < M; ++m)
@@ -231,7 +288,14 @@ __device__ __forceinline__ void potrf_body(T *__restrict__ tiles, int64_t N, int
 template <int B, typename T>
 __global__ __launch_bounds__(256) void potrf_kernel(T *__restrict__ tiles, int64_t N, int64_t c,
                                                     int64_t *__restrict__ info) {
-  potrf_body<B, T>(tiles, N, c, info);
+  potrf_body<B, T, false>(tiles, N, c, info);
+}
+
+// with the fifth-wave lookahead: 320 threads
+template <int B, typename T>
+__global__ __launch_bounds__(320) void potrf_la_kernel(T *__restrict__ tiles, int64_t N,
+                                                       int64_t c, int64_t *__restrict__ info) {
+  potrf_body<B, T, true>(tiles, N, c, info);
 }
 
 // ---------------------------------------------------------------- Step 2 --
@@ -438,13 +502,22 @@ __global__ __launch_bounds__(256) void batch_trsm_kernel(const BatchDesc *__rest
 }
 
 template <int B>
-void potrf_dispatch(void *tiles, int store, int64_t N, int64_t c, int64_t *info, hipStream_t s) {
-  if (store == STORE_F64)
-    hipLaunchKernelGGL((potrf_kernel<B, double>), dim3(1), dim3(256), 0, s, (double *)tiles, N, c,
-                       info);
-  else
+void potrf_dispatch(void *tiles, int store, int64_t N, int64_t c, int64_t *info, hipStream_t s,
+                    bool la) {
+  if (la) {
+    if (store == STORE_F64)
+      hipLaunchKernelGGL((potrf_la_kernel<B, double>), dim3(1), dim3(320), 0, s,
+                         (double *)tiles, N, c, info);
+    else
+      hipLaunchKernelGGL((potrf_la_kernel<B, float>), dim3(1), dim3(320), 0, s, (float *)tiles,
+                         N, c, info);
+  } else if (store == STORE_F64) {
+    hipLaunchKernelGGL((potrf_kernel<B, double>), dim3(1), dim3(256), 0, s, (double *)tiles, N,
+                       c, info);
+  } else {
     hipLaunchKernelGGL((potrf_kernel<B, float>), dim3(1), dim3(256), 0, s, (float *)tiles, N, c,
                        info);
+  }
 }
 
 // Column steps with at most this many tiles below the diagonal split each
@@ -482,12 +555,12 @@ void trsm_dispatch(void *tiles, int store, int64_t N, int64_t c, const int64_t *
 void set_trsm_split_max(int64_t tiles) { g_trsm_split_max = tiles; }
 
 void launch_potrf(void *tiles, int store, int b, int64_t N, int64_t c, int64_t *info,
-                  hipStream_t s) {
+                  hipStream_t s, bool la) {
   if (c < 0 || c >= N) return;  // no such diagonal tile
   if (b == 128)
-    potrf_dispatch<128>(tiles, store, N, c, info, s);
+    potrf_dispatch<128>(tiles, store, N, c, info, s, la);
   else
-    potrf_dispatch<64>(tiles, store, N, c, info, s);
+    potrf_dispatch<64>(tiles, store, N, c, info, s, la);
 }
 
 void launch_diag_inverse(const void *tiles, int store, int b, int64_t N, void *dinv,

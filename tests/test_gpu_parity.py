@@ -209,6 +209,34 @@ def test_trsm_split_bitwise(n, tile):
         P.set_option("trsm_split", old)
 
 
+@pytest.mark.parametrize("n,tile", [(1300, 128), (1000, 64)])
+def test_potrf_lookahead_bitwise(n, tile):
+    """Diagonal-tile factorisation with the fifth-wave lookahead gives the
+    same factor as without it (FP64 and FP32), and reports the same failed
+    pivot."""
+    X, _ = gp_inputs.gp_problem(n, seed=11)
+    A_h = oracle.gp_assemble(X, 1.0, 1.0, 0.1)
+    A = dev(A_h)
+    Abad_h = A_h.copy()
+    Abad_h[n - 37, n - 37] = -1.0
+    _, info_ref = oracle.cholesky(Abad_h)
+    Abad = dev(Abad_h)
+    old = P.get_option("potrf_lookahead")
+    try:
+        for prec in ("fp64", "fp32"):
+            Ls, infos = [], []
+            for la in (0, 1):
+                P.set_option("potrf_lookahead", la)
+                F = P.chol_factor(A, prec, tile)
+                assert F.info() == 0
+                Ls.append(host(P.chol_factor_to_dense(F)))
+                infos.append(P.chol_factor(Abad, prec, tile, sync=False).info())
+            assert np.array_equal(Ls[0], Ls[1])
+            assert infos[0] == infos[1] == info_ref, (prec, infos, info_ref)
+    finally:
+        P.set_option("potrf_lookahead", old)
+
+
 def test_repeatable_bitwise():
     n = 900
     X, _ = gp_inputs.gp_problem(n, seed=4)
