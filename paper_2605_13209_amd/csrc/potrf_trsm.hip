@@ -475,28 +475,33 @@ __global__ __launch_bounds__(256) void diag_inverse_kernel(const T *__restrict__
 
 // Batched column step of several factorisations at once (the serving
 // engine): job j of the descriptor is at tile column c_j of its own packed
-// matrix.  One workgroup per job factors its diagonal tile; the panel solves
-// of all jobs form one flat list that a fixed grid walks.
+// matrix.  One workgroup per job factors its diagonal tile (with the
+// fifth-wave lookahead: the serving orders are small, their column chain is
+// the whole latency); the panel solves of all jobs form one flat list of
+// quarter tiles (a quarter of a tile's rows each) that a fixed grid walks.
 template <int B, typename T>
-__global__ __launch_bounds__(256) void batch_potrf_kernel(const BatchDesc *__restrict__ d) {
+__global__ __launch_bounds__(320) void batch_potrf_kernel(const BatchDesc *__restrict__ d) {
   const int64_t j = blockIdx.x;
   if (j >= d->njobs) return;
   const BatchJob &J = d->jobs[j];
-  potrf_body<B, T>((T *)J.tiles, J.N, J.c, J.info);
+  potrf_body<B, T, true>((T *)J.tiles, J.N, J.c, J.info);
 }
 
 template <int B, typename T>
 __global__ __launch_bounds__(256) void batch_trsm_kernel(const BatchDesc *__restrict__ d) {
-  const int64_t total = d->trsm_total, nj = d->njobs;
-  for (int64_t t = blockIdx.x; t < total; t += gridDim.x) {
+  constexpr int RB = B / 4;
+  const int64_t total = 4 * d->trsm_total, nj = d->njobs;
+  for (int64_t t4 = blockIdx.x; t4 < total; t4 += gridDim.x) {
+    const int64_t t = t4 / 4;
     int64_t j = 0;
     while (j + 1 < nj && d->jobs[j + 1].trsm_begin <= t) ++j;
     const BatchJob &J = d->jobs[j];
     if (*J.info != 0) continue;  // uniform over the workgroup
     T *tiles = (T *)J.tiles;
     const int64_t i = J.c + 1 + (t - J.trsm_begin);
-    trsm_tile<B, T, false>(tiles + tile_index(J.c, J.c, J.N) * (int64_t)(B * B),
-                           tiles + tile_index(i, J.c, J.N) * (int64_t)(B * B));
+    trsm_tile<B, T, false, RB>(tiles + tile_index(J.c, J.c, J.N) * (int64_t)(B * B),
+                               tiles + tile_index(i, J.c, J.N) * (int64_t)(B * B),
+                               (int)(t4 % 4) * RB);
     __syncthreads();  // the tile's LDS is reused by the next one
   }
 }
@@ -585,7 +590,7 @@ void launch_diag_inverse(const void *tiles, int store, int b, int64_t N, void *d
 }
 
 void launch_batch_potrf_trsm(const BatchDesc *d, int max_jobs, int trsm_grid, hipStream_t s) {
-  hipLaunchKernelGGL((batch_potrf_kernel<128, float>), dim3((unsigned)max_jobs), dim3(256), 0, s, d);
+  hipLaunchKernelGGL((batch_potrf_kernel<128, float>), dim3((unsigned)max_jobs), dim3(320), 0, s, d);
   hipLaunchKernelGGL((batch_trsm_kernel<128, float>), dim3((unsigned)trsm_grid), dim3(256), 0, s, d);
 }
 
