@@ -372,8 +372,11 @@ void chol_profile_reset(void);
  *                  (after each tile column, the panel's later columns are
  *                  updated by it), 2 left-looking (before each tile column,
  *                  it is updated by the panel's earlier columns: each panel
- *                  tile read and written once), 0 (default) automatic: 2 for
- *                  CHOL_FP16_SCALED, 1 otherwise.  Same factor bit for bit.
+ *                  tile read and written once), 3 recursive (the panel's
+ *                  columns halved: left half factored, right half updated by
+ *                  it in one launch, then factored; down to two columns),
+ *                  0 (default) automatic: 2 for CHOL_FP16_SCALED, 3 from
+ *                  256 tile rows, 1 otherwise.  Same factor bit for bit.
  * "trsm_split"   : column steps with at most this many tiles below the
  *                  diagonal split each tile's panel solve (Step 2) over four
  *                  workgroups, a quarter of its rows each, which shortens

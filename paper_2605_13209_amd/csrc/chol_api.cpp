@@ -47,7 +47,7 @@ struct Options {
   std::atomic<int64_t> solve_spin_max{1 << 20};  // bound of each wait inside a solve
   std::atomic<int64_t> pcg_recompute{50};  // PCG: true residual every this many iterations
   std::atomic<int64_t> fp16_shift_c{32};   // FP16 retry: diagonal shift c * 2^-11 (0 = no retry)
-  std::atomic<int64_t> panel_order{0};  // in-panel updates: 0 automatic, 1 right-, 2 left-looking
+  std::atomic<int64_t> panel_order{0};  // in-panel updates: 0 auto, 1 right, 2 left, 3 recursive
   std::atomic<int64_t> trsm_split{64};  // panel solves split by rows up to this many tiles
   std::atomic<int64_t> potrf_lookahead{2};  // fifth-wave POTRF: 0 never, 1 always, 2 automatic
 };
@@ -275,7 +275,7 @@ int chol_set_option(const char *key, int64_t value) {
     if (value < 0 || value > 2) return -2;
     g_opt.potrf_lookahead = value;
   } else if (!strcmp(key, "panel_order")) {
-    if (value < 0 || value > 2) return -2;
+    if (value < 0 || value > 3) return -2;
     g_opt.panel_order = value;
   } else if (!strcmp(key, "host_threads")) {
     if (value < 1 || value > 1024) return -2;
@@ -378,37 +378,53 @@ static void *panel_buf(const chol_factor_s *F, size_t p) {
 }
 
 // Steps 1-2 and the in-panel Step 3 of panel number p, columns [c0, c1).
-// The in-panel updates are either right-looking (after column c, one update
-// of the columns c+1 .. c1-1 of the panel by column c) or left-looking
-// (before column c, one update of column c by the columns c0 .. c-1).  Each
-// tile receives the same products in the same order either way (the update
-// kernels add the panel columns in increasing order and store C exactly), so
-// the factor is bitwise the same; left-looking reads and writes each tile of
-// the panel once instead of once per column to its left.
+// The in-panel updates are right-looking (after column c, one update of the
+// columns c+1 .. c1-1 of the panel by column c), left-looking (before column
+// c, one update of column c by the columns c0 .. c-1) or recursive (the
+// columns are halved: the left half is factored, the right half receives
+// the left half's update in one launch, then the right half is factored, in
+// both halves the same way down to two columns).  Each tile receives the
+// same products in the same order in all three (the update kernels add the
+// panel columns in increasing order and store C exactly), so the factor is
+// bitwise the same; left-looking and recursive read and write the panel's
+// tiles fewer times.
 // In the FP16 form each finished tile column is converted into its two
 // chunks of the panel's FP16 buffer right after its panel solve, and the
 // in-panel updates run on the FP16 matrix cores from there, like every
 // other trailing update of that form; the buffer then holds the whole
 // converted panel for the updates right of it.
-static void factor_panel(chol_factor_s *F, size_t p, int64_t c0, int64_t c1, int st,
-                         hipStream_t s) {
+static void factor_columns(chol_factor_s *F, size_t p, int64_t cp0, int64_t c0, int64_t c1, int st,
+                           hipStream_t s) {
   const int64_t N = F->N;
   const int b = F->b;
   const int fp16 = F->p16 ? 1 : 0;
+  // FP16 chunks of the panel's tile column c
+  auto chunks = [&](int64_t c) -> void * {
+    return fp16 ? (char *)panel_buf(F, p) + 2 * (c - cp0) * kP16BytesPerChunk : nullptr;
+  };
+  if (F->inpanel == 2 && c1 - c0 > 2) {
+    const int64_t m = c0 + (c1 - c0) / 2;
+    factor_columns(F, p, cp0, c0, m, st, s);
+    update(F->tiles, st, b, N, c0, (int)(m - c0), m, c1, /*band*/ 1, 8, fp16, F->d_info, s, 0,
+           chunks(c0));
+    factor_columns(F, p, cp0, m, c1, st, s);
+    return;
+  }
   for (int64_t c = c0; c < c1; ++c) {
-    if (F->inpanel_left && c > c0)
+    if (F->inpanel == 1 && c > c0)
       update(F->tiles, st, b, N, c0, (int)(c - c0), c, c + 1, /*band*/ 1, 8, fp16, F->d_info, s, 0,
-             panel_buf(F, p));
+             chunks(c0));
     launch_potrf(F->tiles, st, b, N, c, F->d_info, s, F->potrf_la);
     launch_trsm(F->tiles, st, b, N, c, F->d_info, s);
-    void *col16 = nullptr;
-    if (fp16) {
-      col16 = (char *)panel_buf(F, p) + 2 * (c - c0) * kP16BytesPerChunk;
-      launch_panel_f16(F->tiles, N, c, 1, col16, F->d_info, s);
-    }
-    if (!F->inpanel_left && c + 1 < c1)
-      update(F->tiles, st, b, N, c, 1, c + 1, c1, /*band*/ 1, 8, fp16, F->d_info, s, 0, col16);
+    if (fp16) launch_panel_f16(F->tiles, N, c, 1, chunks(c), F->d_info, s);
+    if (F->inpanel != 1 && c + 1 < c1)
+      update(F->tiles, st, b, N, c, 1, c + 1, c1, /*band*/ 1, 8, fp16, F->d_info, s, 0, chunks(c));
   }
+}
+
+static void factor_panel(chol_factor_s *F, size_t p, int64_t c0, int64_t c1, int st,
+                         hipStream_t s) {
+  factor_columns(F, p, c0, c0, c1, st, s);
 }
 
 // The plain schedule (no lookahead) from tile column c_start on, for a
@@ -581,14 +597,22 @@ int chol_factor_ex(const double *A, int64_t n, int64_t lda, int precision,
   const bool la = la_opt != 0 && N > w;
   const int64_t fw = g_opt.first_panel_width.load();
   const int64_t w0 = fw > 0 ? std::min<int64_t>(fw, w) : w;
-  // in-panel update order (same factor either way).  Automatic: left-looking
-  // for the FP16 form, whose in-panel updates are cheap on the matrix cores
-  // but move FP32 C tiles (n = 131072: 1036 against 1102 ms); right-looking
-  // otherwise, where the longer column chain of left-looking costs more than
-  // the traffic it saves (FP64 n = 1024: 0.90 against 1.26 ms; n = 65536:
-  // 1550 against 1562 ms; FP32 n = 65536 within 0.4 %).
+  // in-panel update order (same factor in all).  Automatic: left-looking for
+  // the FP16 form, whose in-panel updates are cheap on the matrix cores but
+  // move FP32 C tiles (n = 131072: 1036 against 1102 ms right-looking, 1011
+  // against 1019 ms recursive); recursive from 256 tile rows on (FP64
+  // n = 32768: 200.6 against 203.0 ms, n = 65536: 1455.8 against 1466.4 ms;
+  // FP32 n = 65536: 743.1 against 747.3 ms), right-looking below, where the
+  // longer column chain of the other two costs more than the traffic they
+  // save (FP64 n = 1024: 0.77 against 0.86 ms recursive, 1.26 left-looking;
+  // n = 8192: 10.4 against 10.6 ms).
   const int64_t po = g_opt.panel_order.load();
-  F->inpanel_left = po == 2 || (po == 0 && precision == CHOL_FP16_SCALED);
+  F->inpanel = po == 1   ? 0
+               : po == 2 ? 1
+               : po == 3 ? 2
+               : precision == CHOL_FP16_SCALED ? 1
+               : N >= 256                      ? 2
+                                               : 0;
   // diagonal factorisations with the fifth-wave lookahead (same factor):
   // automatic below 64 tile rows, where the column chain is the whole
   // factorisation (n = 1024: 0.86 -> 0.77 ms); from there on the diagonal
@@ -603,7 +627,7 @@ int chol_factor_ex(const double *A, int64_t n, int64_t lda, int precision,
   const bool graph = (opts && opts->graph >= 0 ? opts->graph != 0 : g_opt.graph != 0) &&
                      precision != CHOL_FP16_SCALED && !g_opt.profile && s != nullptr;
   GraphKey gk{A, n, lda, precision, tile, w * 32 + w0,
-              (la ? 1 : 0) + (F->inpanel_left ? 2 : 0) + (F->potrf_la ? 4 : 0), S, workspace};
+              (la ? 1 : 0) + 2 * F->inpanel + (F->potrf_la ? 8 : 0), S, workspace};
   if (graph) {
     int dev = 0;
     (void)hipGetDevice(&dev);

@@ -40,7 +40,7 @@ struct chol_factor_s {
   hipEvent_t ev_solve = nullptr;
   hipStream_t last_solve = nullptr;
   bool solved = false;
-  bool inpanel_left = false;  // in-panel updates left-looking (one per tile column)
+  int inpanel = 0;            // in-panel updates: 0 right-looking, 1 left-looking, 2 recursive
   bool potrf_la = false;      // diagonal factorisations with the fifth-wave lookahead
   // Set by the batched engine: recorded after the factor's last kernel on a
   // stream shared with other work; chol_get_info waits for it instead of

@@ -113,7 +113,7 @@ def test_cg_workspace_bytes():
 
 def test_schedule_options_roundtrip():
     for key, good, bad in (("first_panel_width", 3, 17), ("f16_wide", 0, 2), ("panel_width", 16, 17),
-                           ("bulk_wg_cap", 64, -1), ("solve_spin_max", 100, 0), ("panel_order", 2, 3), ("trsm_split", 0, -1), ("potrf_lookahead", 0, 3)):
+                           ("bulk_wg_cap", 64, -1), ("solve_spin_max", 100, 0), ("panel_order", 3, 4), ("trsm_split", 0, -1), ("potrf_lookahead", 0, 3)):
         old = P.get_option(key)
         P.set_option(key, good)
         assert P.get_option(key) == good

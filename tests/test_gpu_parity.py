@@ -167,10 +167,11 @@ def test_schedule_invariance_bitwise(n, tile):
     A = dev(oracle.gp_assemble(X, 1.0, 1.0, 0.1))
     outs = []
     try:
-        # po: in-panel updates right-looking (1) or left-looking (2)
+        # po: in-panel updates right-looking (1), left-looking (2) or recursive (3)
         for w, la, fw, po in [(1, 0, 0, 1), (2, 1, 0, 2), (4, 1, 0, 1), (4, 1, 0, 2), (3, 0, 0, 2),
                               (8, 1, 0, 1), (8, 1, 0, 2), (6, 0, 0, 1), (16, 1, 0, 2), (8, 1, 2, 2),
-                              (4, 1, 1, 1), (8, 0, 3, 2)]:
+                              (4, 1, 1, 1), (8, 0, 3, 2), (8, 1, 0, 3), (6, 0, 0, 3), (7, 1, 0, 3),
+                              (3, 1, 2, 3)]:
             P.set_option("panel_width", w)
             P.set_option("lookahead", la)
             P.set_option("first_panel_width", fw)
@@ -544,7 +545,7 @@ def test_fp16_scaled_lookahead_invariance(pw, n):
     Ad = P.gp_assemble(torch.from_numpy(X).cuda(), 0.5, 1.0, 1.0)
     Ls = []
     try:
-        for la, po in ((0, 1), (1, 1), (0, 2), (1, 2)):
+        for la, po in ((0, 1), (1, 1), (0, 2), (1, 2), (1, 3)):
             P.set_option("panel_order", po)
             F = P.chol_factor(Ad, "fp16_scaled", 128, panel_width=pw, lookahead=la)
             assert F.info() == 0
