@@ -385,7 +385,7 @@ void chol_profile_reset(void);
  * "potrf_lookahead": 1 factors each diagonal tile (Step 1) with a fifth
  *                  wave that factors the next 16 x 16 diagonal block while
  *                  the other four apply the current block's update; 0
- *                  without; 2 (default) automatic: with it below 64 tile
+ *                  without; 2 (default) automatic: with it up to 64 tile
  *                  rows.  Same factor bit for bit.
  * "bulk_wg_cap"  : with lookahead, the far trailing update runs with at most
  *                  this many (persistent) workgroups, leaving slots for the

@@ -614,13 +614,13 @@ int chol_factor_ex(const double *A, int64_t n, int64_t lda, int precision,
                : N >= 256                      ? 2
                                                : 0;
   // diagonal factorisations with the fifth-wave lookahead (same factor):
-  // automatic below 64 tile rows, where the column chain is the whole
-  // factorisation (n = 1024: 0.86 -> 0.77 ms); from there on the diagonal
-  // factorisation runs beside the trailing update, whose workgroups leave
-  // room for four waves more readily than for five (n = 32768: 203 against
-  // 208 ms with it)
+  // automatic up to 64 tile rows, where the column chain is most of the
+  // factorisation (n = 1024: 0.86 -> 0.77 ms, n = 8192: 10.36 -> 9.66 ms);
+  // beyond, the diagonal factorisation runs beside trailing updates, whose
+  // workgroups leave room for four waves more readily than for five
+  // (n = 16384: 36.7 against 37.1 ms with it, n = 32768: 201.8 against 209.5)
   const int64_t pl = g_opt.potrf_lookahead.load();
-  F->potrf_la = pl == 1 || (pl == 2 && N < 64);
+  F->potrf_la = pl == 1 || (pl == 2 && N <= 64);
 
 
   // Stream capture is not allowed on the legacy NULL stream: direct launches there.
