@@ -122,7 +122,7 @@ int gp_assemble(const double *X, int64_t n, int64_t d, int64_t ldx,
  * lower-triangular and diagonal square blocks, each block contiguous, plus
  * the N inverted diagonal blocks L_cc^{-T} that the solves apply (computed
  * once at the end of the factorisation); CHOL_FP16_SCALED adds two FP16
- * copies of a panel (N * 512 KB each, up to 16 tile columns) that its
+ * copies of a panel (N * 1 MB each, up to 32 tile columns) that its
  * trailing updates read.
  * Returns 0 for invalid arguments.  Host-only; no device work.           */
 size_t chol_factor_bytes(int64_t n, int precision, int tile);
@@ -164,7 +164,7 @@ int chol_factor(const double *A, int64_t n, int64_t lda, int precision,
  * chol_factor with per-call schedule options instead of the process-wide
  * ones (for concurrent callers such as the serving loop).  Any field <= 0
  * (or lookahead < 0) falls back to the process-wide value; opts may be NULL.
- * tile: 64 or 128 (0 = chol_tile_default); panel_width: 1..16 (above 8 only
+ * tile: 64 or 128 (0 = chol_tile_default); panel_width: 1..32 (above 8 only
  * for CHOL_FP16_SCALED; FP64 and FP32 use at most 8); lookahead: 0/1;
  * super_tile: 1..64.  The schedule never changes the computed factor.     */
 typedef struct {
@@ -334,8 +334,8 @@ void chol_profile_reset(void);
 
 /* ---- tuning knobs (process-wide; set before factorising) ---------------
  * "panel_width"  : tiles per outer step whose Step-3 update is applied in
- *                  one pass (1..16; 0 = automatic: 8 from 192 tile rows,
- *                  4 from 64, else 8, and 16 for CHOL_FP16_SCALED from 512
+ *                  one pass (1..32; 0 = automatic: 8 from 192 tile rows,
+ *                  4 from 64, else 8, and 32 for CHOL_FP16_SCALED from 512
  *                  tile rows; default 0).  Widths above 8 apply to
  *                  CHOL_FP16_SCALED only (FP64 and FP32 use 8 then).
  * "lookahead"    : 1 overlaps the next panel's Steps 1-2 with the current
@@ -360,7 +360,7 @@ void chol_profile_reset(void);
  * "host_threads" : threads of the heterogeneous factorisation's CPU share
  *                  (default min(16, hardware threads); only before its first
  *                  call).
- * "first_panel_width": tile columns of the first panel (1..16; 0 = the
+ * "first_panel_width": tile columns of the first panel (1..32; 0 = the
  *                  panel width; default 0).  With lookahead the first
  *                  panel's tile columns are packed first and factored while
  *                  the rest of A is packed; a narrower first panel lets the

@@ -234,7 +234,7 @@ const char *chol_status_string(int status) {
 int chol_set_option(const char *key, int64_t value) {
   if (!key) return -1;
   if (!strcmp(key, "panel_width")) {
-    if (value < 0 || value > 16) return -2;
+    if (value < 0 || value > 32) return -2;
     g_opt.panel_width = value;
   } else if (!strcmp(key, "lookahead")) {
     if (value < 0 || value > 1) return -2;
@@ -255,7 +255,7 @@ int chol_set_option(const char *key, int64_t value) {
     if (value < 0 || value > (int64_t)1 << 30) return -2;
     g_opt.bulk_wg_cap = value;
   } else if (!strcmp(key, "first_panel_width")) {
-    if (value < 0 || value > 16) return -2;
+    if (value < 0 || value > 32) return -2;
     g_opt.first_panel_width = value;
   } else if (!strcmp(key, "f16_wide")) {
     if (value < 0 || value > 1) return -2;
@@ -415,7 +415,10 @@ static void factor_columns(chol_factor_s *F, size_t p, int64_t cp0, int64_t c0, 
       update(F->tiles, st, b, N, c0, (int)(c - c0), c, c + 1, /*band*/ 1, 8, fp16, F->d_info, s, 0,
              chunks(c0));
     launch_potrf(F->tiles, st, b, N, c, F->d_info, s, F->potrf_la);
-    launch_trsm(F->tiles, st, b, N, c, F->d_info, s);
+    if (fp16)
+      launch_trsm_inv(F->tiles, N, c, F->dinv, F->d_info, s);
+    else
+      launch_trsm(F->tiles, st, b, N, c, F->d_info, s);
     if (fp16) launch_panel_f16(F->tiles, N, c, 1, chunks(c), F->d_info, s);
     if (F->inpanel != 1 && c + 1 < c1)
       update(F->tiles, st, b, N, c, 1, c + 1, c1, /*band*/ 1, 8, fp16, F->d_info, s, 0, chunks(c));
@@ -508,8 +511,9 @@ static int enqueue_factor(chol_factor_s *F, SideCtx *ctx, const double *A, int64
     HIP_OK(hipEventRecord(ctx->ev_join, q));
     HIP_OK(hipStreamWaitEvent(s, ctx->ev_join, 0));
   }
-  // inverted diagonal blocks for the solves
-  launch_diag_inverse(F->tiles, st, b, N, F->dinv, F->d_info, s);
+  // inverted diagonal blocks for the solves (the FP16 form has made each one
+  // for its panel solve, right after the diagonal factorisation)
+  if (!fp16) launch_diag_inverse(F->tiles, st, b, N, F->dinv, F->d_info, s);
   return hipGetLastError() == hipSuccess ? CHOL_OK : CHOL_ERR_HIP;
 }
 
@@ -524,7 +528,7 @@ int chol_factor_ex(const double *A, int64_t n, int64_t lda, int precision,
                    const chol_factor_opts *opts, void *workspace, size_t ws_bytes,
                    chol_handle *Fout, int64_t *info, void *stream) {
   int tile = opts ? opts->tile : 0;
-  if (opts && (opts->panel_width > 16 || opts->super_tile > 64 || opts->lookahead > 1)) return -5;
+  if (opts && (opts->panel_width > 32 || opts->super_tile > 64 || opts->lookahead > 1)) return -5;
   if (n > 0 && !A) return -1;
   if (n < 0) return -2;
   if (lda < (n > 1 ? n : 1)) return -3;
@@ -587,7 +591,9 @@ int chol_factor_ex(const double *A, int64_t n, int64_t lda, int precision,
   // automatic width, from the autotuner's sweep on MI355X: 8 for small
   // (chain-bound) and large matrices, 4 in between
   int64_t w = pw_opt > 0 ? pw_opt : (N >= 192 ? 8 : (N >= 64 ? 4 : 8));
-  if (pw_opt <= 0 && precision == CHOL_FP16_SCALED && N >= 512) w = 16;  // 10 % faster at n = 131072
+  // FP16 form from 512 tile rows: 32 (n = 131072: factor 901 ms against 909
+  // with 24, 967 with 16, 1070 with 8)
+  if (pw_opt <= 0 && precision == CHOL_FP16_SCALED && N >= 512) w = 32;
   if (precision != CHOL_FP16_SCALED && w > 8) w = 8;
   const int S =
       (int)((opts && opts->super_tile > 0) ? (int64_t)opts->super_tile : g_opt.super_tile.load());
@@ -626,7 +632,7 @@ int chol_factor_ex(const double *A, int64_t n, int64_t lda, int precision,
   // Stream capture is not allowed on the legacy NULL stream: direct launches there.
   const bool graph = (opts && opts->graph >= 0 ? opts->graph != 0 : g_opt.graph != 0) &&
                      precision != CHOL_FP16_SCALED && !g_opt.profile && s != nullptr;
-  GraphKey gk{A, n, lda, precision, tile, w * 32 + w0,
+  GraphKey gk{A, n, lda, precision, tile, w * 64 + w0,
               (la ? 1 : 0) + 2 * F->inpanel + (F->potrf_la ? 8 : 0), S, workspace};
   if (graph) {
     int dev = 0;

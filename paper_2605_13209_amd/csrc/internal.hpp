@@ -107,14 +107,19 @@ void launch_update(void *tiles, int store, int b, int64_t N, int64_t p0, int pw,
 // per workgroup, the default; 0: one tile per workgroup).  Same result.
 void set_f16_wide(int on);
 // FP16 copy of the finished panel columns [c0, c0 + pw) for tile rows
-// [c0, N), in the update kernel's layout: p16 holds N * 32 chunks of
+// [c0, N), in the update kernel's layout: p16 holds N * 64 chunks of
 // 128 x 64 halves per panel buffer (two 64-column chunks per tile column of
-// the panel, panel width <= 16).
+// the panel, panel width <= 32).
 constexpr int64_t kP16BytesPerChunk = 128 * 64 * 2;  // 128 rows x 64 columns of halves
-constexpr int64_t kP16BytesPerTileRow = 32 * kP16BytesPerChunk;
+constexpr int64_t kP16BytesPerTileRow = 64 * kP16BytesPerChunk;
 void launch_panel_f16(const void *tiles, int64_t N, int64_t c0, int pw, void *p16,
                       const int64_t *info, hipStream_t s);
 
+// Step 2 of the FP16 form (FP32 tiles, tile 128): block c of dinv <- L_cc^{-T}
+// (as launch_diag_inverse computes it), then the tiles (i, c), i > c, <-
+// tile * dinv_c on the FP32 matrix cores.
+void launch_trsm_inv(void *tiles, int64_t N, int64_t c, void *dinv, const int64_t *info,
+                     hipStream_t s);
 // After the factorisation: block c of dinv (N blocks of b x b) = L_cc^{-T}.
 void launch_diag_inverse(const void *tiles, int store, int b, int64_t N, void *dinv,
                          const int64_t *info, hipStream_t s);

@@ -466,11 +466,78 @@ __global__ __launch_bounds__(256) void trsm_kernel(T *__restrict__ tiles, int64_
 template <int B, typename T>
 __global__ __launch_bounds__(256) void diag_inverse_kernel(const T *__restrict__ tiles, int64_t N,
                                                            T *__restrict__ dinv,
-                                                           const int64_t *__restrict__ info) {
+                                                           const int64_t *__restrict__ info,
+                                                           int64_t c0) {
   if (*info != 0) return;
-  const int64_t c = blockIdx.x;
+  const int64_t c = c0 + blockIdx.x;
   trsm_tile<B, T, true>(tiles + tile_index(c, c, N) * (int64_t)(B * B),
                         dinv + c * (int64_t)(B * B));
+}
+
+// Panel solve of the FP16 form through the inverted diagonal block: for the
+// tiles (i, c), i in (c, N), X = A D with D = L_cc^{-T} (block c of dinv,
+// column-major, computed right after the diagonal factorisation; the solves
+// use the same blocks), as one FP32 matrix-core product per tile
+// (v_mfma_f32_16x16x4_f32, the lane layout of the FP32 trailing update:
+// acc[s2][u][e] = X(64 wm + 16 g + 4 e + s2, 64 wn + 4 q + u)).  A is staged
+// as stored, D transposed (the B operand at contraction index k, output
+// column s is D(k, s)), 32 columns at a time.  The tile is overwritten only
+// after all of it has been read.  A matrix-core product instead of 128
+// dependent substitution steps: the FP16 form's panel solves run beside its
+// trailing updates, and this way they hold a CU for a fraction of the time.
+__global__ __launch_bounds__(256) void trsm_inv_kernel(float *__restrict__ tiles, int64_t N,
+                                                       int64_t c, const float *__restrict__ D,
+                                                       const int64_t *__restrict__ info) {
+  constexpr int B = 128, KC = 32;
+  typedef float v4f __attribute__((ext_vector_type(4)));
+  if (*info != 0) return;
+  const int64_t i = c + 1 + blockIdx.x;
+  float *X = tiles + tile_index(i, c, N) * (int64_t)(B * B);
+  const float *Dc = D + c * (int64_t)(B * B);
+  __shared__ __attribute__((aligned(16))) float la[KC * B], lb[KC * B];  // [k][row or column]
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int g = lane >> 4, q = lane & 15, wm = wave >> 1, wn = wave & 1;
+  v4f acc[4][4];
+#pragma unroll
+  for (int s2 = 0; s2 < 4; ++s2)
+#pragma unroll
+    for (int u = 0; u < 4; ++u) acc[s2][u] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 1
+  for (int k0 = 0; k0 < B; k0 += KC) {
+    // A: columns k0 .. k0+31 of the tile, contiguous
+#pragma unroll
+    for (int x = 0; x < KC * B / 1024; ++x) {
+      const int e = 4 * (tid + 256 * x);
+      *(v4f *)&la[e] = *(const v4f *)&X[(int64_t)k0 * B + e];
+    }
+    // D transposed: lb[kk * B + s] = D(k0 + kk, s) = Dc[s * B + k0 + kk]
+#pragma unroll
+    for (int x = 0; x < KC * B / 1024; ++x) {
+      const int e = tid + 256 * x, sc = e / (KC / 4), kk = 4 * (e % (KC / 4));
+      const v4f v = *(const v4f *)&Dc[(int64_t)sc * B + k0 + kk];
+#pragma unroll
+      for (int y = 0; y < 4; ++y) lb[(kk + y) * B + sc] = v[y];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ks = 0; ks < KC / 4; ++ks) {
+      const v4f fa = *(const v4f *)&la[(4 * ks + g) * B + 64 * wm + 4 * q];
+      const v4f fb = *(const v4f *)&lb[(4 * ks + g) * B + 64 * wn + 4 * q];
+#pragma unroll
+      for (int s2 = 0; s2 < 4; ++s2)
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          acc[s2][u] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[s2], fb[u], acc[s2][u], 0, 0, 0);
+    }
+    __syncthreads();  // the chunk's LDS is refilled next
+  }
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const v4f v = {acc[0][u][e], acc[1][u][e], acc[2][u][e], acc[3][u][e]};
+      *(v4f *)&X[(int64_t)(64 * wn + 4 * q + u) * B + 64 * wm + 16 * g + 4 * e] = v;
+    }
 }
 
 // Batched column step of several factorisations at once (the serving
@@ -568,6 +635,16 @@ void launch_potrf(void *tiles, int store, int b, int64_t N, int64_t c, int64_t *
     potrf_dispatch<64>(tiles, store, N, c, info, s, la);
 }
 
+void launch_trsm_inv(void *tiles, int64_t N, int64_t c, void *dinv, const int64_t *info,
+                     hipStream_t s) {
+  if (c < 0 || c >= N) return;
+  hipLaunchKernelGGL((diag_inverse_kernel<128, float>), dim3(1), dim3(256), 0, s,
+                     (const float *)tiles, N, (float *)dinv, info, c);
+  if (N - c - 1 > 0)
+    hipLaunchKernelGGL(trsm_inv_kernel, dim3((unsigned)(N - c - 1)), dim3(256), 0, s,
+                       (float *)tiles, N, c, (const float *)dinv, info);
+}
+
 void launch_diag_inverse(const void *tiles, int store, int b, int64_t N, void *dinv,
                          const int64_t *info, hipStream_t s) {
   if (N <= 0) return;
@@ -575,17 +652,17 @@ void launch_diag_inverse(const void *tiles, int store, int b, int64_t N, void *d
   if (b == 128) {
     if (store == STORE_F64)
       hipLaunchKernelGGL((diag_inverse_kernel<128, double>), grid, dim3(256), 0, s,
-                         (const double *)tiles, N, (double *)dinv, info);
+                         (const double *)tiles, N, (double *)dinv, info, (int64_t)0);
     else
       hipLaunchKernelGGL((diag_inverse_kernel<128, float>), grid, dim3(256), 0, s,
-                         (const float *)tiles, N, (float *)dinv, info);
+                         (const float *)tiles, N, (float *)dinv, info, (int64_t)0);
   } else {
     if (store == STORE_F64)
       hipLaunchKernelGGL((diag_inverse_kernel<64, double>), grid, dim3(256), 0, s,
-                         (const double *)tiles, N, (double *)dinv, info);
+                         (const double *)tiles, N, (double *)dinv, info, (int64_t)0);
     else
       hipLaunchKernelGGL((diag_inverse_kernel<64, float>), grid, dim3(256), 0, s,
-                         (const float *)tiles, N, (float *)dinv, info);
+                         (const float *)tiles, N, (float *)dinv, info, (int64_t)0);
   }
 }
 

@@ -410,7 +410,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void u
 // FP32 kernel, wave-local row 4q + s2) hit 8 different 16-byte bank groups
 // per 8 lanes.  Converting once per panel instead of once per use also
 // removes the transpose from the update's inner loop.
-constexpr int P16_CHMAX = 32;  // chunks of 64 columns per tile row (panel width <= 16)
+constexpr int P16_CHMAX = 64;  // chunks of 64 columns per tile row (panel width <= 32)
 constexpr int P16_CHUNK = BT * 64;  // halves per chunk
 
 // Position (in halves) of row r, 16-byte segment sg of a converted chunk.

@@ -40,9 +40,9 @@ def test_factor_bytes():
     assert P.chol_factor_bytes(1024, "fp64", 128) == 512 + (36 + 8) * 128 * 128 * 8
     assert P.chol_factor_bytes(1000, "fp32", 128) == 512 + (36 + 8) * 128 * 128 * 4
     assert P.chol_factor_bytes(65536, "fp64", 128) == 512 + (512 * 513 // 2 + 512) * 128 * 128 * 8
-    # FP16 form: FP32 tiles plus two FP16 panel buffers of N * 32 chunks of 128 x 64 halves
+    # FP16 form: FP32 tiles plus two FP16 panel buffers of N * 64 chunks of 128 x 64 halves
     assert P.chol_factor_bytes(1024, "fp16_scaled", 128) == \
-        512 + (36 + 8) * 128 * 128 * 4 + 2 * 8 * 32 * 128 * 64 * 2
+        512 + (36 + 8) * 128 * 128 * 4 + 2 * 8 * 64 * 128 * 64 * 2
     assert P.chol_factor_bytes(0, "fp64", 64) == 512
     assert P.chol_factor_bytes(10, "fp64", 96) == 0
     assert P.chol_factor_bytes(-1, "fp64", 64) == 0
@@ -55,7 +55,7 @@ def test_options_roundtrip_and_validation():
     assert P.get_option("panel_width") == 4
     P.set_option("panel_width", old)
     with pytest.raises(P.CholError):
-        P.set_option("panel_width", 17)
+        P.set_option("panel_width", 33)
     with pytest.raises(P.CholError):
         P.set_option("no_such_knob", 1)
     assert P.get_option("no_such_knob") == -1
@@ -112,7 +112,7 @@ def test_cg_workspace_bytes():
 
 
 def test_schedule_options_roundtrip():
-    for key, good, bad in (("first_panel_width", 3, 17), ("f16_wide", 0, 2), ("panel_width", 16, 17),
+    for key, good, bad in (("first_panel_width", 3, 33), ("f16_wide", 0, 2), ("panel_width", 32, 33),
                            ("bulk_wg_cap", 64, -1), ("solve_spin_max", 100, 0), ("panel_order", 3, 4), ("trsm_split", 0, -1), ("potrf_lookahead", 0, 3)):
         old = P.get_option(key)
         P.set_option(key, good)

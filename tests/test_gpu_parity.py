@@ -535,12 +535,12 @@ def test_fp16_scaled_factor_and_refine():
             assert err <= 1e-10, (method, c, err)
 
 
-@pytest.mark.parametrize("pw,n", [(2, 1300), (3, 1300), (16, 2250)])
+@pytest.mark.parametrize("pw,n", [(2, 1300), (3, 1300), (16, 2250), (32, 4500)])
 def test_fp16_scaled_lookahead_invariance(pw, n):
     # the two FP16 panel buffers alternate between panels; with and without
     # lookahead (ragged n, a partial last panel), with right- and left-looking
-    # in-panel updates, the factors are identical; width 16 (the FP16 form's
-    # widest: 32 chunks of 64 columns per tile row)
+    # in-panel updates, the factors are identical; width 32 (the FP16 form's
+    # widest: 64 chunks of 64 columns per tile row) with a full first panel
     X, _ = gp_inputs.gp_problem(n, seed=4)
     Ad = P.gp_assemble(torch.from_numpy(X).cuda(), 0.5, 1.0, 1.0)
     Ls = []
