@@ -388,8 +388,8 @@ static void *panel_buf(const chol_factor_s *F, size_t p) {
 // panel columns in increasing order and store C exactly), so the factor is
 // bitwise the same; left-looking and recursive read and write the panel's
 // tiles fewer times.
-// In the FP16 form each finished tile column is converted into its two
-// chunks of the panel's FP16 buffer right after its panel solve, and the
+// In the FP16 form the panel solve also writes each finished tile column in
+// FP16 into its two chunks of the panel's FP16 buffer, and the
 // in-panel updates run on the FP16 matrix cores from there, like every
 // other trailing update of that form; the buffer then holds the whole
 // converted panel for the updates right of it.
@@ -416,10 +416,9 @@ static void factor_columns(chol_factor_s *F, size_t p, int64_t cp0, int64_t c0, 
              chunks(c0));
     launch_potrf(F->tiles, st, b, N, c, F->d_info, s, F->potrf_la);
     if (fp16)
-      launch_trsm_inv(F->tiles, N, c, F->dinv, F->d_info, s);
+      launch_trsm_inv(F->tiles, N, c, F->dinv, chunks(c), F->d_info, s);
     else
       launch_trsm(F->tiles, st, b, N, c, F->d_info, s);
-    if (fp16) launch_panel_f16(F->tiles, N, c, 1, chunks(c), F->d_info, s);
     if (F->inpanel != 1 && c + 1 < c1)
       update(F->tiles, st, b, N, c, 1, c + 1, c1, /*band*/ 1, 8, fp16, F->d_info, s, 0, chunks(c));
   }

@@ -95,8 +95,8 @@ void launch_trsm(void *tiles, int store, int b, int64_t N, int64_t c, const int6
 //   mode 0 (triangle): k0 <= k <= i < N;
 //   mode 1 (band)    : k in [k0, k1), k <= i < N  (k1 - k0 <= super_tile);
 //   mode 2 (rectangle, FP64 tile 128): i in [r0, N), k in [k0, k1), r0 >= k1.
-// fp16 = 1 takes the panel operands in FP16 from p16, the panel converted
-// by launch_panel_f16 (FP32 storage, tile 128 only).
+// fp16 = 1 takes the panel operands in FP16 from p16, the panel's FP16 copy
+// written by launch_trsm_inv (FP32 storage, tile 128 only).
 // max_wg > 0 caps the number of workgroups (each then walks several tiles),
 // leaving workgroup slots free for kernels on other streams.
 void launch_update(void *tiles, int store, int b, int64_t N, int64_t p0, int pw, int64_t k0,
@@ -106,20 +106,36 @@ void launch_update(void *tiles, int store, int b, int64_t N, int64_t p0, int pw,
 // Kernel choice for the FP16 form's whole-triangle updates (1: 2 x 2 tiles
 // per workgroup, the default; 0: one tile per workgroup).  Same result.
 void set_f16_wide(int on);
-// FP16 copy of the finished panel columns [c0, c0 + pw) for tile rows
-// [c0, N), in the update kernel's layout: p16 holds N * 64 chunks of
-// 128 x 64 halves per panel buffer (two 64-column chunks per tile column of
-// the panel, panel width <= 32).
+// FP16 panel buffers of the FP16 form: for tile row i and chunk ch (64
+// columns of the panel, two per tile column), 128 rows x 64 halves at halves
+// offset (i * kP16ChunksPerTileRow + ch) * 128 * 64, up to 32 tile columns
+// per panel.  Within a chunk, row r's 16-byte segment sg (columns 8 sg ..
+// 8 sg + 7) sits at p16_pos(r, sg).
+constexpr int kP16ChunksPerTileRow = 64;
 constexpr int64_t kP16BytesPerChunk = 128 * 64 * 2;  // 128 rows x 64 columns of halves
-constexpr int64_t kP16BytesPerTileRow = 64 * kP16BytesPerChunk;
-void launch_panel_f16(const void *tiles, int64_t N, int64_t c0, int pw, void *p16,
-                      const int64_t *info, hipStream_t s);
+constexpr int64_t kP16BytesPerTileRow = kP16ChunksPerTileRow * kP16BytesPerChunk;
+
+// The update kernels' FP16 fragment reads (v_mfma_f32_16x16x32_f16: lane
+// (g, q) supplies row 4q + s2 of the operand, columns 8g .. 8g + 7) have the
+// 16 lanes of a lane group on rows 4q + s2, q = 0..15.  Segments are
+// XOR-swizzled by q mod 8, and the stored row takes bit 5 of the logical row
+// (the high bit of q) as its bit 0, so the sixteen lanes cover both 128-byte
+// halves of a 256-byte line of all 64 LDS banks with distinct segments: one
+// 128-bit read is conflict-free.  The low two row bits (s2) move to bits 4-5
+// so that the four rows a lane reads differ by constant offsets.  The chunks
+// are DMA'd verbatim, so the LDS layout equals this one.
+__device__ __forceinline__ int p16_pos(int r, int sg) {
+  const int pr = (r & 64) | ((r & 3) << 4) | (((r >> 2) & 7) << 1) | ((r >> 5) & 1);
+  return pr * 64 + 8 * (sg ^ ((r >> 2) & 7));
+}
 
 // Step 2 of the FP16 form (FP32 tiles, tile 128): block c of dinv <- L_cc^{-T}
 // (as launch_diag_inverse computes it), then the tiles (i, c), i > c, <-
-// tile * dinv_c on the FP32 matrix cores.
-void launch_trsm_inv(void *tiles, int64_t N, int64_t c, void *dinv, const int64_t *info,
-                     hipStream_t s);
+// tile * dinv_c on the FP32 matrix cores, each also written in FP16 to its
+// two chunks of the panel buffer p16c (the chunks of tile column c, tile row
+// 0; the diagonal tile's chunks, which no update reads, are left alone).
+void launch_trsm_inv(void *tiles, int64_t N, int64_t c, void *dinv, void *p16c,
+                     const int64_t *info, hipStream_t s);
 // After the factorisation: block c of dinv (N blocks of b x b) = L_cc^{-T}.
 void launch_diag_inverse(const void *tiles, int store, int b, int64_t N, void *dinv,
                          const int64_t *info, hipStream_t s);

@@ -482,19 +482,25 @@ __global__ __launch_bounds__(256) void diag_inverse_kernel(const T *__restrict__
 // acc[s2][u][e] = X(64 wm + 16 g + 4 e + s2, 64 wn + 4 q + u)).  A is staged
 // as stored, D transposed (the B operand at contraction index k, output
 // column s is D(k, s)), 32 columns at a time.  The tile is overwritten only
-// after all of it has been read.  A matrix-core product instead of 128
-// dependent substitution steps: the FP16 form's panel solves run beside its
-// trailing updates, and this way they hold a CU for a fraction of the time.
+// after all of it has been read.  X then goes once more, rounded to FP16,
+// into the tile's two 64-column chunks of the panel buffer (p16c: the chunks
+// of tile column c for tile row 0), through LDS, one chunk at a time.  A
+// matrix-core product instead of 128 dependent substitution steps: the FP16
+// form's panel solves run beside its trailing updates, and this way they hold
+// a CU for a fraction of the time.
 __global__ __launch_bounds__(256) void trsm_inv_kernel(float *__restrict__ tiles, int64_t N,
                                                        int64_t c, const float *__restrict__ D,
+                                                       _Float16 *__restrict__ p16c,
                                                        const int64_t *__restrict__ info) {
-  constexpr int B = 128, KC = 32;
+  constexpr int B = 128, KC = 32, PAD = B + 1;
   typedef float v4f __attribute__((ext_vector_type(4)));
+  typedef _Float16 v8h __attribute__((ext_vector_type(8)));
   if (*info != 0) return;
   const int64_t i = c + 1 + blockIdx.x;
   float *X = tiles + tile_index(i, c, N) * (int64_t)(B * B);
   const float *Dc = D + c * (int64_t)(B * B);
   __shared__ __attribute__((aligned(16))) float la[KC * B], lb[KC * B];  // [k][row or column]
+  __shared__ float st[64 * PAD];                                         // [column][row]
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int g = lane >> 4, q = lane & 15, wm = wave >> 1, wn = wave & 1;
   v4f acc[4][4];
@@ -538,6 +544,30 @@ __global__ __launch_bounds__(256) void trsm_inv_kernel(float *__restrict__ tiles
       const v4f v = {acc[0][u][e], acc[1][u][e], acc[2][u][e], acc[3][u][e]};
       *(v4f *)&X[(int64_t)(64 * wn + 4 * q + u) * B + 64 * wm + 16 * g + 4 * e] = v;
     }
+  // FP16 copy: columns 64 h .. 64 h + 63 (the waves with wn == h) through LDS
+#pragma unroll 1
+  for (int h = 0; h < 2; ++h) {
+    if (wn == h) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+#pragma unroll
+          for (int s2 = 0; s2 < 4; ++s2)
+            st[(4 * q + u) * PAD + 64 * wm + 16 * g + 4 * e + s2] = acc[s2][u][e];
+    }
+    __syncthreads();
+    _Float16 *dst = p16c + (i * kP16ChunksPerTileRow + h) * (int64_t)(B * 64);
+#pragma unroll
+    for (int x = 0; x < 4; ++x) {
+      const int e = tid + 256 * x, r = e / 8, sg = e % 8;
+      v8h v;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) v[j] = (_Float16)st[(8 * sg + j) * PAD + r];
+      *(v8h *)(dst + p16_pos(r, sg)) = v;
+    }
+    __syncthreads();  // st is refilled for the second chunk
+  }
 }
 
 // Batched column step of several factorisations at once (the serving
@@ -635,14 +665,14 @@ void launch_potrf(void *tiles, int store, int b, int64_t N, int64_t c, int64_t *
     potrf_dispatch<64>(tiles, store, N, c, info, s, la);
 }
 
-void launch_trsm_inv(void *tiles, int64_t N, int64_t c, void *dinv, const int64_t *info,
-                     hipStream_t s) {
+void launch_trsm_inv(void *tiles, int64_t N, int64_t c, void *dinv, void *p16c,
+                     const int64_t *info, hipStream_t s) {
   if (c < 0 || c >= N) return;
   hipLaunchKernelGGL((diag_inverse_kernel<128, float>), dim3(1), dim3(256), 0, s,
                      (const float *)tiles, N, (float *)dinv, info, c);
   if (N - c - 1 > 0)
     hipLaunchKernelGGL(trsm_inv_kernel, dim3((unsigned)(N - c - 1)), dim3(256), 0, s,
-                       (float *)tiles, N, c, (const float *)dinv, info);
+                       (float *)tiles, N, c, (const float *)dinv, (_Float16 *)p16c, info);
 }
 
 void launch_diag_inverse(const void *tiles, int store, int b, int64_t N, void *dinv,

@@ -401,59 +401,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void u
 }
 
 // --------------------------------------------------- FP16 operands (FP32 C) --
-// The FP16 form converts each finished panel once (panel_f16_kernel) into a
-// buffer laid out for the update: for tile row i and chunk ch (64 panel
-// columns), 128 rows x 128 bytes, row r's 16-byte segment s (k = 8s .. 8s+7)
-// stored at position s ^ ((r >> 2) & 7).  The update kernel then DMAs 16 KB
-// chunks straight into LDS, and its fragment reads (v_mfma_f32_16x16x32_f16:
-// lane (g, q) supplies A[row q][k = 8g .. 8g+7]; rows interleaved as in the
-// FP32 kernel, wave-local row 4q + s2) hit 8 different 16-byte bank groups
-// per 8 lanes.  Converting once per panel instead of once per use also
-// removes the transpose from the update's inner loop.
-constexpr int P16_CHMAX = 64;  // chunks of 64 columns per tile row (panel width <= 32)
-constexpr int P16_CHUNK = BT * 64;  // halves per chunk
-
-// Position (in halves) of row r, 16-byte segment sg of a converted chunk.
-// A fragment read has the 16 lanes of one lane group on rows 4q + s2
-// (q = 0..15) of one operand.  Segments are XOR-swizzled by q mod 8, and the
-// stored row takes bit 5 of the logical row (the high bit of q) as its bit 0,
-// so the sixteen lanes cover both 128-byte halves of a 256-byte line of all
-// 64 LDS banks with distinct segments: one 128-bit read is conflict-free.
-// The low two row bits (s2) move to bits 4-5 so that the four rows a lane
-// reads differ by constant offsets.  The update kernels DMA chunks verbatim,
-// so the LDS layout equals this one.
-__device__ __forceinline__ int p16_pos(int r, int sg) {
-  const int pr = (r & 64) | ((r & 3) << 4) | (((r >> 2) & 7) << 1) | ((r >> 5) & 1);
-  return pr * 64 + 8 * (sg ^ ((r >> 2) & 7));
-}
-
-__global__ __launch_bounds__(256) void panel_f16_kernel(const float *__restrict__ tiles, int64_t N,
-                                                        int64_t c0, _Float16 *__restrict__ p16,
-                                                        const int64_t *__restrict__ info) {
-  if (*info != 0) return;
-  constexpr int PAD = BT + 1;
-  __shared__ float st[64 * PAD];  // [column][row]
-  const int64_t i = c0 + blockIdx.x;
-  const int ch = blockIdx.y;
-  const int64_t p = c0 + ch / 2;
-  const int t = threadIdx.x;
-  if (p <= i) {
-    const float *src = tiles + tile_index(i, p, N) * (int64_t)(BT * BT) + (ch % 2) * 64 * BT;
-    for (int e = t; e < 64 * BT; e += 256) st[(e / BT) * PAD + e % BT] = src[e];
-  } else {
-    for (int e = t; e < 64 * BT; e += 256) st[(e / BT) * PAD + e % BT] = 0.0f;
-  }
-  __syncthreads();
-  _Float16 *dst = p16 + (i * P16_CHMAX + ch) * (int64_t)P16_CHUNK;
-#pragma unroll
-  for (int x = 0; x < 4; ++x) {
-    const int e = t + 256 * x, r = e / 8, sg = e % 8;
-    v8h v;
-#pragma unroll
-    for (int j = 0; j < 8; ++j) v[j] = (_Float16)st[(8 * sg + j) * PAD + r];
-    *(v8h *)(dst + p16_pos(r, sg)) = v;
-  }
-}
+// The FP16 form's panel solve writes each finished tile column once more in
+// FP16, into the panel buffer in the layout of p16_pos (internal.hpp): the
+// update kernels DMA its 16 KB chunks straight into LDS, where their fragment
+// reads are conflict-free, and no transpose is left in the inner loop.
+constexpr int P16_CHMAX = kP16ChunksPerTileRow;  // chunks of 64 columns per tile row
+constexpr int P16_CHUNK = BT * 64;               // halves per chunk
 
 // Trailing update with FP16 operands from the converted panel and FP32 C
 // (accumulators start at -C).  Same structure as the FP32 kernel: chunks of
@@ -896,13 +849,6 @@ void launch_batch_update(const BatchDesc *d, int upd_grid, int super_tile, hipSt
   hipLaunchKernelGGL(update_f32_kernel<3>, dim3((unsigned)(upd_grid / 8 * 8)), dim3(256), 0, s,
                      (float *)d, (int64_t)0, (int64_t)0, 1, (int64_t)0, (int64_t)0, super_tile,
                      (int64_t)0, (int64_t)0, (const int64_t *)nullptr);
-}
-
-void launch_panel_f16(const void *tiles, int64_t N, int64_t c0, int pw, void *p16,
-                      const int64_t *info, hipStream_t s) {
-  if (N - c0 <= 0 || pw <= 0) return;
-  hipLaunchKernelGGL(panel_f16_kernel, dim3((unsigned)(N - c0), (unsigned)(2 * pw)), dim3(256), 0,
-                     s, (const float *)tiles, N, c0, (_Float16 *)p16, info);
 }
 
 }  // namespace chol
