@@ -29,7 +29,11 @@ __device__ inline void two_sum(double a, double b, double &s, double &e) {
 // |A||x| even at n ~ 1e5.  Every reduction has a fixed order.  Contraction is
 // off in the kernel: a product fused into the following TwoSum (hs + av * xv
 // as one fma) would make the error terms count the product's rounding twice.
-template <int NR>
+// DD = false: the same walk with plain FP64 accumulation (one fma per product,
+// error within the usual recursive-summation bound n u |A||x|), for the
+// refinement's working residuals and CG products; HBM-bound where the
+// double-double form is bound by FP64 arithmetic (several right-hand sides).
+template <int NR, bool DD>
 __global__ __launch_bounds__(256) void symm_residual_kernel(
     const double *__restrict__ A, int64_t lda, int64_t n, const double *__restrict__ X,
     int64_t ldx, const double *__restrict__ Bm, int64_t ldb, double *__restrict__ R, int64_t ldr,
@@ -116,12 +120,16 @@ __global__ __launch_bounds__(256) void symm_residual_kernel(
 #pragma unroll
         for (int cc = 0; cc < NR; ++cc) {
           const double xv = xb[jj * NR + cc];
-          const double p = av * xv;
-          const double pe = fma(av, xv, -p);
-          double s1, e1;
-          two_sum(hs[u][cc], p, s1, e1);
-          hs[u][cc] = s1;
-          he[u][cc] += e1 + pe;
+          if (DD) {
+            const double p = av * xv;
+            const double pe = fma(av, xv, -p);
+            double s1, e1;
+            two_sum(hs[u][cc], p, s1, e1);
+            hs[u][cc] = s1;
+            he[u][cc] += e1 + pe;
+          } else {
+            hs[u][cc] = fma(av, xv, hs[u][cc]);
+          }
         }
       }
     }
@@ -254,15 +262,22 @@ __global__ void pcg_beta_kernel(const double *__restrict__ rho_new, double *__re
 
 void launch_symm_residual(const double *A, int64_t lda, int64_t n, const double *X, int64_t ldx,
                           const double *B, int64_t ldb, double *R, int64_t ldr, int64_t nrhs,
-                          hipStream_t s) {
+                          hipStream_t s, bool exact) {
   if (n <= 0 || nrhs <= 0) return;
   const unsigned gx = (unsigned)((n + 63) / 64);
-  if (nrhs == 1)
-    hipLaunchKernelGGL(symm_residual_kernel<1>, dim3(gx, 1), dim3(256), 0, s, A, lda, n, X, ldx,
+  const dim3 g1(gx, 1), g8(gx, (unsigned)((nrhs + 7) / 8));
+  if (nrhs == 1 && exact)
+    hipLaunchKernelGGL((symm_residual_kernel<1, true>), g1, dim3(256), 0, s, A, lda, n, X, ldx,
+                       B, ldb, R, ldr, nrhs);
+  else if (nrhs == 1)
+    hipLaunchKernelGGL((symm_residual_kernel<1, false>), g1, dim3(256), 0, s, A, lda, n, X, ldx,
+                       B, ldb, R, ldr, nrhs);
+  else if (exact)
+    hipLaunchKernelGGL((symm_residual_kernel<8, true>), g8, dim3(256), 0, s, A, lda, n, X, ldx,
                        B, ldb, R, ldr, nrhs);
   else
-    hipLaunchKernelGGL(symm_residual_kernel<8>, dim3(gx, (unsigned)((nrhs + 7) / 8)), dim3(256),
-                       0, s, A, lda, n, X, ldx, B, ldb, R, ldr, nrhs);
+    hipLaunchKernelGGL((symm_residual_kernel<8, false>), g8, dim3(256), 0, s, A, lda, n, X, ldx,
+                       B, ldb, R, ldr, nrhs);
 }
 
 void launch_col_dot(const double *x, int64_t ldx, const double *y, int64_t ldy, int64_t n,

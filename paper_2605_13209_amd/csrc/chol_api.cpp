@@ -16,6 +16,7 @@
 // without these options, so results are bitwise identical across them.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <atomic>
 #include <chrono>
 #include <cmath>
@@ -878,11 +879,12 @@ struct Refiner {
     if (e != hipSuccess && rc == CHOL_OK) rc = CHOL_ERR_HIP;
     return rc == CHOL_OK;
   }
-  // out = B - A x (or -A x when rhs is false)
-  void residual(const double *x, int64_t ldxx, double *out, bool rhs = true) {
+  // out = B - A x (or -A x when rhs is false); exact = false: plain FP64
+  // accumulation instead of double-double (stored A only)
+  void residual(const double *x, int64_t ldxx, double *out, bool rhs = true, bool exact = true) {
     const double *Bm = rhs ? B : nullptr;
     if (A)
-      launch_symm_residual(A, lda, n, x, ldxx, Bm, ldb, out, n, k, s);
+      launch_symm_residual(A, lda, n, x, ldxx, Bm, ldb, out, n, k, s, exact);
     else
       launch_gp_residual(Xf, n, d, ldxf, two_l2, var, noise, x, ldxx, Bm, ldb, out, n, k, s);
   }
@@ -919,14 +921,38 @@ struct Refiner {
   }
 
   // Iterative refinement.  Returns true when PCG should take over (a column
-  // whose correction failed to halve twice in a row: stagnation).
+  // whose correction failed to halve twice in a row: stagnation).  With a
+  // certificate and a stored A the working residuals are plain FP64; the
+  // residual is taken again in double-double before any column is judged
+  // (as soon as one passes on the working residual, and at the iteration
+  // limit), and for good once a column stalls, so every certificate comes
+  // from a double-double residual.  When the last certificate times the last
+  // contraction of the corrections predicts a pass for every active column
+  // (with a factor 2 to spare), the residual is taken in double-double at
+  // once instead of twice.
   bool run_ir(int max_iter) {
-    std::vector<double> dprev(k, INFINITY);
+    std::vector<double> dprev(k, INFINITY), ratio(k, INFINITY);
     std::vector<int> stall(k, 0);
+    bool fast = certify && A != nullptr;
     if (!upload(act, h_act)) return false;
     for (;;) {
-      residual(X, ldx, r);
+      bool exact = !fast;
+      if (fast && iters >= 2) {
+        exact = true;
+        for (int64_t c = 0; c < k; ++c)
+          if (h_act[c] && !(cert[c] * ratio[c] <= 0.25 * tol)) exact = false;
+      }
+      residual(X, ldx, r, true, exact);
       if (!norms(iters > 0)) return false;
+      if (!exact) {
+        bool judge = iters >= max_iter;
+        for (int64_t c = 0; c < k; ++c)
+          if (h_act[c] && cert_of(c) <= 0.5 * tol) judge = true;
+        if (judge) {
+          residual(X, ldx, r, true, true);
+          if (!norms(iters > 0)) return false;
+        }
+      }
       bool changed = false;
       for (int64_t c = 0; c < k; ++c) {
         if (!h_act[c]) continue;
@@ -949,12 +975,19 @@ struct Refiner {
             }
           }
           stall[c] = dn > 0.5 * dprev[c] ? stall[c] + 1 : 0;
+          if (std::isfinite(dprev[c]) && dprev[c] > 0.0) ratio[c] = dn / dprev[c];
           dprev[c] = dn;
         }
       }
       if (active_count() == 0 || iters >= max_iter) return false;
+      bool stalled = false;
       for (int64_t c = 0; c < k; ++c)
-        if (h_act[c] && stall[c] >= 2) return true;
+        if (h_act[c] && stall[c] >= 2) stalled = true;
+      if (stalled) {
+        if (!fast) return true;
+        fast = false;  // perhaps at the working residual's rounding level
+        std::fill(stall.begin(), stall.end(), 0);
+      }
       if (changed && !upload(act, h_act)) return false;
       launch_copy(r, n, z, n, n, k, s);
       msolve(z);
@@ -981,7 +1014,7 @@ struct Refiner {
     launch_copy(z, n, p, n, n, k, s);
     launch_col_dot(r, n, z, n, n, k, rho, partial, s);
     for (int64_t it = 1; iters < max_iter; ++it) {
-      residual(p, n, q, false);                                        // q = -A p
+      residual(p, n, q, false, false);                                 // q = -A p
       launch_col_dot(p, n, q, n, n, k, pq, partial, s);
       launch_pcg_alpha(rho, pq, act, alpha, k, s);                     // rho / p.Ap
       launch_axpby(p, n, X, ldx, n, k, alpha, 1.0, nullptr, act, s);  // x += alpha p

@@ -150,10 +150,12 @@ void launch_solve(const void *tiles, const void *dinv, int store, int b, int64_t
 // Scale B by alpha in place (used by the scaled-FP16 factor).
 void launch_scale(double *B, int64_t n, int64_t ldb, int64_t nrhs, double alpha, hipStream_t s);
 
-// R = B - A X, A symmetric from its lower triangle.
+// R = B - A X, A symmetric from its lower triangle; exact: double-double
+// accumulation (the residuals that certify), else plain FP64 (the working
+// residuals of the refinement and the CG products).
 void launch_symm_residual(const double *A, int64_t lda, int64_t n, const double *X,
                           int64_t ldx, const double *B, int64_t ldb, double *R, int64_t ldr,
-                          int64_t nrhs, hipStream_t s);
+                          int64_t nrhs, hipStream_t s, bool exact = true);
 // Per-column squared 2-norms and dot products into out[nrhs] (deterministic).
 void launch_col_dot(const double *x, int64_t ldx, const double *y, int64_t ldy, int64_t n,
                     int64_t nrhs, double *out, double *partial, hipStream_t s);
