@@ -55,16 +55,16 @@ sys.path.insert(0, ROOT)
 # C tile read and written once, each panel tile read once, averaged over the
 # launches of one factorisation (panel width 8; width 32 for FP16).
 TRAFFIC_RECORDS = {
-    ("f64", 65536): {"update_hip_sha256_16": "b0da0d572028c4c6", "bytes_per_launch": 3.280e10,
+    ("f64", 65536): {"update_hip_sha256_16": "8c934b5e35c6ab2e", "bytes_per_launch": 3.283e10,
                      "algorithmic_bytes_per_launch": 1.131e10,
                      "source": "profiles/update_f64_kernel_traffic_n65536.md"},
-    ("f64", 32768): {"update_hip_sha256_16": "b0da0d572028c4c6", "bytes_per_launch": 7.902e9,
+    ("f64", 32768): {"update_hip_sha256_16": "8c934b5e35c6ab2e", "bytes_per_launch": 7.901e9,
                      "algorithmic_bytes_per_launch": 2.790e9,
                      "source": "profiles/update_f64_kernel_traffic_n32768.md"},
-    ("f32", 65536): {"update_hip_sha256_16": "b0da0d572028c4c6", "bytes_per_launch": 1.714e10,
+    ("f32", 65536): {"update_hip_sha256_16": "8c934b5e35c6ab2e", "bytes_per_launch": 1.708e10,
                      "algorithmic_bytes_per_launch": 5.65e9,
                      "source": "profiles/update_f32_kernel_traffic_n65536.md"},
-    ("f16", 131072): {"update_hip_sha256_16": "b0da0d572028c4c6", "bytes_per_launch": 6.996e10,
+    ("f16", 131072): {"update_hip_sha256_16": "8c934b5e35c6ab2e", "bytes_per_launch": 6.997e10,
                       "algorithmic_bytes_per_launch": 2.170e10,
                       "source": "profiles/update_f16_wide_kernel_traffic_n131072.md"},
 }
