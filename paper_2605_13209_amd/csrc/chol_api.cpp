@@ -929,11 +929,14 @@ struct Refiner {
   // from a double-double residual.  When the last certificate times the last
   // contraction of the corrections predicts a pass for every active column
   // (with a factor 2 to spare), the residual is taken in double-double at
-  // once instead of twice.
+  // once instead of twice; when a plain residual's certificate lies far
+  // (16x) above that prediction, the plain residuals have reached their own
+  // rounding level and the rest are taken in double-double.  With one
+  // right-hand side both forms are bound by HBM: double-double throughout.
   bool run_ir(int max_iter) {
     std::vector<double> dprev(k, INFINITY), ratio(k, INFINITY);
     std::vector<int> stall(k, 0);
-    bool fast = certify && A != nullptr;
+    bool fast = certify && A != nullptr && k > 1;
     if (!upload(act, h_act)) return false;
     for (;;) {
       bool exact = !fast;
@@ -946,8 +949,12 @@ struct Refiner {
       if (!norms(iters > 0)) return false;
       if (!exact) {
         bool judge = iters >= max_iter;
-        for (int64_t c = 0; c < k; ++c)
-          if (h_act[c] && cert_of(c) <= 0.5 * tol) judge = true;
+        for (int64_t c = 0; c < k; ++c) {
+          if (!h_act[c]) continue;
+          const double ce = cert_of(c);
+          if (ce <= 0.5 * tol) judge = true;
+          if (iters >= 2 && ce > 16.0 * cert[c] * ratio[c]) judge = true, fast = false;
+        }
         if (judge) {
           residual(X, ldx, r, true, true);
           if (!norms(iters > 0)) return false;
@@ -1014,7 +1021,7 @@ struct Refiner {
     launch_copy(z, n, p, n, n, k, s);
     launch_col_dot(r, n, z, n, n, k, rho, partial, s);
     for (int64_t it = 1; iters < max_iter; ++it) {
-      residual(p, n, q, false, false);                                 // q = -A p
+      residual(p, n, q, false, k == 1);                                // q = -A p
       launch_col_dot(p, n, q, n, n, k, pq, partial, s);
       launch_pcg_alpha(rho, pq, act, alpha, k, s);                     // rho / p.Ap
       launch_axpby(p, n, X, ldx, n, k, alpha, 1.0, nullptr, act, s);  // x += alpha p

@@ -147,6 +147,24 @@ def test_ir_without_stagnation_keeps_ir():
     assert res.converged and res.fallback_used == 0 and 1 <= res.iters <= 6
 
 
+def test_ir_several_rhs_below_the_plain_residual_floor():
+    """With several right-hand sides IR's working residuals are plain FP64;
+    here their rounding (about sqrt(n) u |A||x|) lies far above the
+    certificate's threshold (noise 1e-4), so the certifying residuals must
+    be double-double: the call still certifies every column, and the
+    certificate holds for the exactly computed residual."""
+    n, k, noise = 512, 2, 1e-4
+    X, B = gp_inputs.gp_problem(n, seed=7, k=k)
+    A = oracle.gp_assemble(X, 1.0, 1.0, noise)
+    Ad = dev(A)
+    F = P.chol_factor(Ad, "fp32", 128)
+    res = P.chol_refine_solve(F, dev(B), A=Ad, noise=noise, tol=1e-10, max_iter=200, method="ir")
+    assert res.converged
+    x = host(res.X)
+    for c in range(k):
+        assert true_cert(A, B[:, c], x[:, c], noise) <= 0.5e-10 * (1 + 1e-6)
+
+
 def _fp16_failing_problem(noise):
     # smooth SE kernel (lengthscale 2): the smallest eigenvalue of the scaled
     # matrix is about the noise, far below the FP16 update's rounding error
