@@ -479,14 +479,16 @@ static int enqueue_factor(chol_factor_s *F, SideCtx *ctx, const double *A, int64
     }
   } else {
     // the first panel's tile columns are packed first and factored on the
-    // side stream while the main stream packs the rest
+    // side stream while the main stream packs the rest (enqueued before the
+    // first panel's launches, so that it need not wait for the host to issue
+    // them)
     hipStream_t q = ctx->side;
     launch_pack(A, n, lda, F->tiles, st, b, N, pack_scale, s, 0, pb[1], sh);
     HIP_OK(hipEventRecord(ctx->ev_fork, s));
     HIP_OK(hipStreamWaitEvent(q, ctx->ev_fork, 0));
-    factor_panel(F, 0, 0, pb[1], st, q);
     launch_pack(A, n, lda, F->tiles, st, b, N, pack_scale, s, pb[1], N, sh);
     HIP_OK(hipEventRecord(ctx->ev_bulk, s));  // everything packed
+    factor_panel(F, 0, 0, pb[1], st, q);
     for (size_t p = 0; p < P; ++p) {
       const int64_t c0 = pb[p], c1 = pb[p + 1];   // current panel [c0, c1)
       const int64_t n1 = p + 2 <= P ? pb[p + 2] : N;  // next panel [c1, n1)
