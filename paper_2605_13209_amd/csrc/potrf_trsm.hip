@@ -322,7 +322,6 @@ __global__ __launch_bounds__(320) void potrf_la_kernel(T *__restrict__ tiles, in
 // updates shrink with the rows, while the row solves (2) keep their length.
 template <int B, typename T, bool IDENT, int RB = B>
 __device__ __forceinline__ void trsm_tile(const T *__restrict__ L, T *__restrict__ X, int r0 = 0) {
-  static_assert(!IDENT || RB == B, "the identity right-hand side is solved whole");
   constexpr int M = B / 16, MR = RB / 16, NB = 16, PP = NB + 2;
   constexpr int PF = (B * NB + 255) / 256;                  // prefetched L values per thread
   __shared__ __attribute__((aligned(16))) double ls[2][B * PP];  // L column blocks
@@ -349,9 +348,9 @@ __device__ __forceinline__ void trsm_tile(const T *__restrict__ L, T *__restrict
   double a[MR][M];
   if (IDENT) {
 #pragma unroll
-    for (int m = 0; m < M; ++m)
+    for (int m = 0; m < MR; ++m)
 #pragma unroll
-      for (int n = 0; n < M; ++n) a[m][n] = (tr + 16 * m == tc + 16 * n) ? 1.0 : 0.0;
+      for (int n = 0; n < M; ++n) a[m][n] = (r0 + tr + 16 * m == tc + 16 * n) ? 1.0 : 0.0;
   } else {
     // the rows into registers through LDS (the L buffers, not yet in use),
     // 32 columns at a time with contiguous reads, the next group's loads in
@@ -462,16 +461,18 @@ __global__ __launch_bounds__(256) void trsm_kernel(T *__restrict__ tiles, int64_
 }
 
 // Inverted diagonal blocks for the solves: block c of dinv = L_cc^{-T}
-// (column-major), one workgroup per diagonal tile.
-template <int B, typename T>
+// (column-major), B / RB workgroups per diagonal tile, each solving RB rows
+// of the identity (the rows are independent, as in the panel solve).
+template <int B, typename T, int RB = B>
 __global__ __launch_bounds__(256) void diag_inverse_kernel(const T *__restrict__ tiles, int64_t N,
                                                            T *__restrict__ dinv,
                                                            const int64_t *__restrict__ info,
                                                            int64_t c0) {
   if (*info != 0) return;
-  const int64_t c = c0 + blockIdx.x;
-  trsm_tile<B, T, true>(tiles + tile_index(c, c, N) * (int64_t)(B * B),
-                        dinv + c * (int64_t)(B * B));
+  constexpr int SPLIT = B / RB;
+  const int64_t c = c0 + blockIdx.x / SPLIT;
+  trsm_tile<B, T, true, RB>(tiles + tile_index(c, c, N) * (int64_t)(B * B),
+                            dinv + c * (int64_t)(B * B), (int)(blockIdx.x % SPLIT) * RB);
 }
 
 // Panel solve of the FP16 form through the inverted diagonal block: for the
@@ -668,7 +669,7 @@ void launch_potrf(void *tiles, int store, int b, int64_t N, int64_t c, int64_t *
 void launch_trsm_inv(void *tiles, int64_t N, int64_t c, void *dinv, void *p16c,
                      const int64_t *info, hipStream_t s) {
   if (c < 0 || c >= N) return;
-  hipLaunchKernelGGL((diag_inverse_kernel<128, float>), dim3(1), dim3(256), 0, s,
+  hipLaunchKernelGGL((diag_inverse_kernel<128, float, 32>), dim3(4), dim3(256), 0, s,
                      (const float *)tiles, N, (float *)dinv, info, c);
   if (N - c - 1 > 0)
     hipLaunchKernelGGL(trsm_inv_kernel, dim3((unsigned)(N - c - 1)), dim3(256), 0, s,
@@ -678,21 +679,37 @@ void launch_trsm_inv(void *tiles, int64_t N, int64_t c, void *dinv, void *p16c,
 void launch_diag_inverse(const void *tiles, int store, int b, int64_t N, void *dinv,
                          const int64_t *info, hipStream_t s) {
   if (N <= 0) return;
-  const dim3 grid((unsigned)N);
+  // a quarter of the rows per workgroup where the launch is latency-bound
+  // (the split's four workgroups cost more CU time than one)
+  const bool split = N <= g_trsm_split_max;
+  const dim3 grid((unsigned)(split ? 4 * N : N));
+  const int64_t z = 0;
   if (b == 128) {
-    if (store == STORE_F64)
+    if (store == STORE_F64 && split)
+      hipLaunchKernelGGL((diag_inverse_kernel<128, double, 32>), grid, dim3(256), 0, s,
+                         (const double *)tiles, N, (double *)dinv, info, z);
+    else if (store == STORE_F64)
       hipLaunchKernelGGL((diag_inverse_kernel<128, double>), grid, dim3(256), 0, s,
-                         (const double *)tiles, N, (double *)dinv, info, (int64_t)0);
+                         (const double *)tiles, N, (double *)dinv, info, z);
+    else if (split)
+      hipLaunchKernelGGL((diag_inverse_kernel<128, float, 32>), grid, dim3(256), 0, s,
+                         (const float *)tiles, N, (float *)dinv, info, z);
     else
       hipLaunchKernelGGL((diag_inverse_kernel<128, float>), grid, dim3(256), 0, s,
-                         (const float *)tiles, N, (float *)dinv, info, (int64_t)0);
+                         (const float *)tiles, N, (float *)dinv, info, z);
   } else {
-    if (store == STORE_F64)
+    if (store == STORE_F64 && split)
+      hipLaunchKernelGGL((diag_inverse_kernel<64, double, 16>), grid, dim3(256), 0, s,
+                         (const double *)tiles, N, (double *)dinv, info, z);
+    else if (store == STORE_F64)
       hipLaunchKernelGGL((diag_inverse_kernel<64, double>), grid, dim3(256), 0, s,
-                         (const double *)tiles, N, (double *)dinv, info, (int64_t)0);
+                         (const double *)tiles, N, (double *)dinv, info, z);
+    else if (split)
+      hipLaunchKernelGGL((diag_inverse_kernel<64, float, 16>), grid, dim3(256), 0, s,
+                         (const float *)tiles, N, (float *)dinv, info, z);
     else
       hipLaunchKernelGGL((diag_inverse_kernel<64, float>), grid, dim3(256), 0, s,
-                         (const float *)tiles, N, (float *)dinv, info, (int64_t)0);
+                         (const float *)tiles, N, (float *)dinv, info, z);
   }
 }
 

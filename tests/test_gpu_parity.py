@@ -193,19 +193,22 @@ def test_schedule_invariance_bitwise(n, tile):
 @pytest.mark.parametrize("n,tile", [(1300, 128), (1000, 64)])
 def test_trsm_split_bitwise(n, tile):
     """Panel solves split over four workgroups per tile (a quarter of the rows
-    each) give the same factor as whole-tile panel solves."""
-    X, _ = gp_inputs.gp_problem(n, seed=9)
+    each) give the same factor as whole-tile panel solves, and the inverted
+    diagonal blocks split the same way give the same solves."""
+    X, Bm = gp_inputs.gp_problem(n, seed=9, k=3)
     A = dev(oracle.gp_assemble(X, 1.0, 1.0, 0.1))
     old = P.get_option("trsm_split")
     try:
         for prec in ("fp64", "fp32"):
-            Ls = []
+            Ls, Xs = [], []
             for split in (0, 1 << 20, 3):
                 P.set_option("trsm_split", split)
                 F = P.chol_factor(A, prec, tile)
                 assert F.info() == 0
                 Ls.append(host(P.chol_factor_to_dense(F)))
+                Xs.append(host(P.chol_solve(F, dev(Bm))))
             assert np.array_equal(Ls[0], Ls[1]) and np.array_equal(Ls[0], Ls[2])
+            assert np.array_equal(Xs[0], Xs[1]) and np.array_equal(Xs[0], Xs[2])
     finally:
         P.set_option("trsm_split", old)
 
