@@ -925,7 +925,7 @@ struct Refiner {
   // Iterative refinement.  Returns true when PCG should take over (a column
   // whose correction failed to halve twice in a row: stagnation).  With a
   // certificate and a stored A the working residuals are plain FP64; the
-  // residual is taken again in double-double before any column is judged
+  // residual is taken again in double-double before any column is tested
   // (as soon as one passes on the working residual, and at the iteration
   // limit), and for good once a column stalls, so every certificate comes
   // from a double-double residual.  When the last certificate times the last
@@ -950,14 +950,14 @@ struct Refiner {
       residual(X, ldx, r, true, exact);
       if (!norms(iters > 0)) return false;
       if (!exact) {
-        bool judge = iters >= max_iter;
+        bool confirm = iters >= max_iter;
         for (int64_t c = 0; c < k; ++c) {
           if (!h_act[c]) continue;
           const double ce = cert_of(c);
-          if (ce <= 0.5 * tol) judge = true;
-          if (iters >= 2 && ce > 16.0 * cert[c] * ratio[c]) judge = true, fast = false;
+          if (ce <= 0.5 * tol) confirm = true;
+          if (iters >= 2 && ce > 16.0 * cert[c] * ratio[c]) confirm = true, fast = false;
         }
-        if (judge) {
+        if (confirm) {
           residual(X, ldx, r, true, true);
           if (!norms(iters > 0)) return false;
         }
