@@ -223,7 +223,12 @@ size_t chol_refine_bytes(int64_t n, int64_t nrhs, int method);
  * Solve A X = B to FP64 accuracy with a (typically low-precision) factor F
  * of A, by iterative refinement (method CHOL_REFINE_IR) or by CG
  * preconditioned with M = F F^T (CHOL_REFINE_PCG).  Residuals r = b - A x
- * and the solution updates are computed in FP64.
+ * and the solution updates are computed in FP64; every residual a
+ * certificate is taken from is accumulated in double-double, and with a
+ * stored A, lam > 0 and several right-hand sides the working residuals of
+ * IR and the products q = A p of PCG are plain FP64 (IR takes the residual
+ * again in double-double before a column can stop, at the iteration limit,
+ * and for good once the plain residuals stop improving).
  * A      : device, FP64 n x n column-major (lower triangle read), lda; or
  *          NULL, in which case the residual is computed matrix-free from the
  *          GP features Xf (n x d row-major, ldxf) and the hyper-parameters,
